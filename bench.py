@@ -1,0 +1,153 @@
+"""Benchmark: FP64 cell-updates/s of the fused explicit step on one MI355X.
+
+Workload: Fenton-Karma 3-variable model on a 1024 x 1024 grid, isotropic
+9-point Laplacian (Eq. 6), classical RK4, dx = 0.025 cm, dt = 0.1 ms,
+D = 0.001 cm^2/ms, broken-wave spiral seed.  One benchmark "step" is one RK4
+time step of the whole grid (one fused kernel launch).  Inputs are resident
+in HBM before the timed region; the state is advanced in place.
+
+Prints one JSON line (see the keys below).  --gpus N with N > 1 exits: this
+build runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
+FP64_VECTOR_PEAK = 78.6e12  # flop/s, MI355X FP64 vector (FMA = 2 flops)
+KERNEL_SOURCES = ["paper_1309_1720_amd/csrc/rd_device.h", "paper_1309_1720_amd/csrc/rd_fwd.h"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "fwd_fk_1024_rk4_counters.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cells: int):
+    """HBM bytes per launch from committed rocprofv3 counters, if they were
+    taken on the current kernel sources; else None."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    with open(COUNTERS_FILE) as fh:
+        c = json.load(fh)
+    if c.get("kernel_sha") != kernel_hash() or c.get("cells") != cells:
+        return None
+    return c.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, params, seconds: float):
+    """The oracle as it stands, on the host, over a bounded number of steps."""
+    import numpy as np
+    import oracle
+    import rd_inputs as ri
+    po = oracle.Problem.from_workload(w, params=params)
+    z = ri.initial_condition(w)
+    z = oracle.step(po, z, 1)  # warm-up
+    n, t0 = 0, time.perf_counter()
+    while True:
+        z = oracle.step(po, z, 1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or n >= 1000:
+            break
+    rate = w["nx"] * w["ny"] * n / el
+    return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} RK4 steps of the {w['nx']}x{w['ny']} Fenton-Karma grid "
+                      f"(NumPy, single thread), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1309_1720_amd as rd
+    import rd_inputs as ri
+
+    w = ri.workload("fk_1024_rk4")
+    params = ri.params_array("fk")
+    nx, ny = w["nx"], w["ny"]
+    cells = nx * ny
+    nv = ri.N_FIELDS["fk"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    if args.tile_rows:
+        rd.set_tile_rows(args.tile_rows)
+    p = rd.Problem.from_workload(w, params, nsteps=args.warmup)
+    if args.warmup:
+        rd.step(p, z)
+    torch.cuda.synchronize()
+
+    p.nsteps = args.steps
+    stream = torch.cuda.current_stream(dev)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    rd.step(p, z)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    sec = ms / 1e3
+    if not all(bool(torch.isfinite(t).all()) for t in z):
+        raise RuntimeError("non-finite state after the timed steps")
+
+    rate = cells * args.steps / sec
+    bytes_per_launch = 2 * nv * 8 * cells  # read and write the state once
+    launch_s = sec / args.steps            # one fused kernel per step
+    achieved = bytes_per_launch / launch_s
+    out = {
+        "metric": "FP64 cell-updates/s",
+        "value": rate,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fenton_karma_1024x1024_lap9_rk4", "nx": nx, "ny": ny,
+                   "stencil": "lap9", "scheme": "rk4", "dx": w["dx"], "dt": w["dt"],
+                   "D": w["D_par"], "fields": nv},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                     "traffic": measured_traffic(cells),
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": launch_s * 1e6},
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, params, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

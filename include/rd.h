@@ -1,0 +1,196 @@
+/*
+ * rd.h -- C ABI of librd.so, an MI355X (gfx950) library that advances 2-D
+ * cardiac reaction-diffusion systems
+ *
+ *     dz/dt = div(D grad z) + N[z],   z = (u, h1, h2, ...),
+ *
+ * in double precision with a fully explicit finite-difference time step.
+ * The method is that of Marcotte & Grigoriev, "Implementation of PDE models
+ * of cardiac dynamics on GPUs using OpenCL" (arXiv:1309.1720): Eq. (1) with
+ * no-flux boundaries (Eq. 2) on an N x N Cartesian grid (Sect. 3), the
+ * diffusion operator as a 5-point or 9-point stencil (Eq. 6) whose
+ * out-of-domain points take the adjacent boundary value (Fig. 1), and
+ * explicit Euler, Heun or classical fourth-order Runge-Kutta stages
+ * (Sect. 3, Sect. 4).  Only the voltage u diffuses.
+ *
+ * Conventions shared by every entry point
+ *   - Fields are FP64, one contiguous array per field ("structure of
+ *     arrays"), row-major [ny][nx] with x fastest, 8-byte aligned, on the
+ *     current HIP device.  Cell (i, j) has centre ((i + 1/2) dx, (j + 1/2) dx).
+ *   - Field order is the model's: Barkley (u, v); Fenton-Karma (u, v, w);
+ *     Bueno-Orovio (u, v, w, s); diffusion (u).
+ *   - All field, tangent, cotangent, checkpoint and workspace pointers are
+ *     DEVICE pointers owned by the caller.  rd_problem and its params array
+ *     are HOST memory, read during the call only.
+ *   - The library never allocates device memory.  Scratch space comes from
+ *     the caller's workspace, whose size rd_workspace_bytes() reports.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the default
+ *     stream) and the call returns without synchronising.  Argument errors
+ *     are detected on the host before anything is enqueued; a device fault
+ *     surfaces at the caller's next synchronisation.
+ *   - Return value: RD_OK (0) or a negative rd_status.  rd_last_error()
+ *     then returns a message for the calling thread.  No C++ exception
+ *     crosses this interface.
+ *   - Distinct pointers passed in one call must not alias.
+ */
+#ifndef RD_H
+#define RD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RD_ABI_VERSION 1
+
+/* Models (Sect. 2; the Barkley and Fenton-Karma models are additions). */
+enum rd_model {
+  RD_MODEL_DIFFUSION = 0,    /* N = 0, one field; a test model              */
+  RD_MODEL_BARKLEY = 1,      /* 2 fields; params: a, b, eps                  */
+  RD_MODEL_FENTON_KARMA = 2, /* 3 fields; params: tau_v+, tau_v1-, tau_v2-,
+                                tau_w+, tau_w-, tau_d, tau_0, tau_r, tau_si,
+                                k_si, u_c_si, u_c, u_v                       */
+  RD_MODEL_BOCF = 3          /* 4 fields (Eq. 5); params: u_o, u_u, theta_v,
+                                theta_w, theta_v-, theta_o, tau_v1-, tau_v2-,
+                                tau_v+, tau_w1-, tau_w2-, k_w-, u_w-, tau_w+,
+                                tau_fi, tau_o1, tau_o2, tau_so1, tau_so2,
+                                k_so, u_so, tau_s1, tau_s2, k_s, u_s, tau_si,
+                                tau_w_inf, w_inf_star                        */
+};
+
+/* Explicit schemes (Sect. 3): Euler (1 stage), Heun (2), classical RK4 (4). */
+enum rd_scheme { RD_SCHEME_EULER = 1, RD_SCHEME_HEUN = 2, RD_SCHEME_RK4 = 4 };
+
+/* Diffusion operators.
+ *   RD_LAP5       D (W + E + N + S - 4C) / dx^2.
+ *   RD_LAP9       Eq. (6): axial weight 2/3, diagonal weight 1/6, centre
+ *                 balanced, times D / dx^2.
+ *   RD_LAP9_ANISO div(D grad u) in conservative flux form for the tensor
+ *                 D = D_perp I + (D_par - D_perp) f f^T, f = (cos t, sin t),
+ *                 t linear in x from theta0 (x = 0) to theta1 (x = nx dx);
+ *                 zero flux through the domain boundary. */
+enum rd_stencil { RD_LAP5 = 5, RD_LAP9 = 9, RD_LAP9_ANISO = 10 };
+
+/* Boundary conditions: no-flux (Eq. 2) via mirrored ghost cells (Fig. 1). */
+enum rd_bc { RD_BC_NOFLUX = 0 };
+
+/* Operations, for rd_workspace_bytes(). */
+enum rd_op { RD_OP_STEP = 0, RD_OP_JVP = 1, RD_OP_VJP = 2, RD_OP_BATCHED = 3 };
+
+enum rd_status {
+  RD_OK = 0,
+  RD_EINVAL = -1,       /* invalid argument (null pointer, bad size, ...)     */
+  RD_EUNSUPPORTED = -2, /* valid but unsupported combination                  */
+  RD_EWORKSPACE = -3,   /* workspace missing or smaller than required         */
+  RD_EHIP = -4          /* HIP runtime error (message holds the HIP string)   */
+};
+
+/* One integration problem (the problem statement of Sect. 3). */
+typedef struct rd_problem {
+  uint32_t abi_version;   /* must equal RD_ABI_VERSION                        */
+  int32_t model;          /* rd_model                                         */
+  int32_t scheme;         /* rd_scheme                                        */
+  int32_t stencil;        /* rd_stencil                                       */
+  int32_t bc;             /* rd_bc                                            */
+  int32_t nx, ny;         /* grid cells, each >= 1, nx * ny < 2^31            */
+  double dx;              /* grid spacing (dy == dx), > 0                     */
+  double dt;              /* time step, > 0                                   */
+  int64_t nsteps;         /* steps to take, >= 0 (0 is a no-op)               */
+  double D_par;           /* diffusivity (isotropic stencils use only this)   */
+  double D_perp;          /* cross-fibre diffusivity, RD_LAP9_ANISO only      */
+  double theta0, theta1;  /* fibre angle (radians), RD_LAP9_ANISO only        */
+  double step_k;          /* sharpness k of the smoothed step H_k (Sect. 2),
+                             > 0; +INFINITY selects the Heaviside step with
+                             H(0) = 1                                         */
+  const double* params;   /* host array of model parameters (order above)     */
+  int32_t nparams;        /* its length; must match the model                 */
+  int32_t checkpoint_every; /* rd_step: store the state every this many steps
+                             into `checkpoints` (0 = none); rd_vjp: the
+                             spacing of the checkpoints it is given            */
+} rd_problem;
+
+/* ABI version the library was built with (RD_ABI_VERSION). */
+int rd_abi_version(void);
+
+/* Number of fields of `model`, or RD_EINVAL. */
+int rd_n_fields(int32_t model);
+
+/* Number of parameters of `model`, or RD_EINVAL. */
+int rd_n_params(int32_t model);
+
+/* Number of checkpoint states rd_step writes for this problem:
+ * ceil(nsteps / checkpoint_every), 0 when checkpoint_every == 0.
+ * Checkpoint m is the state after m * checkpoint_every steps, stored as
+ * [m][field][ny][nx]. */
+int rd_checkpoint_count(const rd_problem* p, int64_t* out);
+
+/* Bytes of device workspace `op` needs for problem `p` (for RD_OP_BATCHED,
+ * `p` points to `nbatch` problems -- see rd_step_batched_workspace_bytes). */
+int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out);
+
+/*
+ * rd_step -- advance the state by p->nsteps explicit steps, in place.
+ *   fields       host array of n_fields device pointers; read as z(0),
+ *                overwritten with z(nsteps).
+ *   checkpoints  device array of rd_checkpoint_count(p) states, or NULL;
+ *                receives z(m * checkpoint_every).
+ *   ws, ws_bytes caller workspace, >= rd_workspace_bytes(p, RD_OP_STEP).
+ * Each step is one fused kernel: every stage's stencil, reaction and
+ * Euler-like update (Sect. 4) over an on-chip tile.
+ */
+int rd_step(const rd_problem* p, double* const* fields, double* checkpoints,
+            void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * rd_jvp -- tangent-linear map of the finite-time flow (an addition to the
+ * paper, motivated by its Newton-Krylov use case, Sect. 1).  Advances the
+ * state z and a tangent dz together by p->nsteps steps, in place:
+ *   fields    z(0) -> z(nsteps)
+ *   tangents  dz(0) -> dPhi(z(0)) dz(0), the exact derivative of the
+ *             discrete nsteps-step map.
+ */
+int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents,
+           void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * rd_vjp -- adjoint of the finite-time flow (an addition to the paper).
+ *   checkpoints  the states rd_step stored for the same problem (same
+ *                nsteps and checkpoint_every > 0); only read.
+ *   cotangents   host array of n_fields device pointers; read as
+ *                lambda(nsteps), overwritten with
+ *                lambda(0) = dPhi(z(0))^T lambda(nsteps).
+ * States between checkpoints are recomputed into the workspace.
+ * Supports RD_LAP5 and RD_LAP9 (RD_LAP9_ANISO returns RD_EUNSUPPORTED).
+ */
+int rd_vjp(const rd_problem* p, const double* checkpoints, double* const* cotangents,
+           void* ws, size_t ws_bytes, void* hip_stream);
+
+/*
+ * rd_step_batched -- advance `nbatch` independent problems (same model,
+ * scheme and stencil; grids, dx, dt, D and parameters may differ; all with
+ * the same nsteps) in one launch per step (an addition to the paper).
+ *   fields[b]    host array of n_fields device pointers of problem b.
+ *   tangents     NULL for a forward-only run, else tangents[b] as in
+ *                rd_jvp: the tangents are advanced with the states.
+ * Results equal per-problem rd_step / rd_jvp bit for bit.
+ */
+int rd_step_batched_workspace_bytes(const rd_problem* probs, int32_t nbatch,
+                                    int32_t with_tangents, size_t* out);
+int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* const* fields,
+                    double* const* const* tangents, void* ws, size_t ws_bytes,
+                    void* hip_stream);
+
+/* Rows per wavefront band used by later calls from any thread (<= 0:
+ * automatic choice).  A performance knob: results do not depend on it. */
+int rd_set_tile_rows(int32_t rows);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* rd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RD_H */

@@ -1,0 +1,12 @@
+"""MI355X-native explicit time stepping of 2-D cardiac reaction-diffusion
+models in FP64 (Marcotte & Grigoriev, arXiv:1309.1720).
+
+The computation lives in the HIP library ``librd.so`` (C ABI in
+``include/rd.h``); this package is its thin Python binding.  PyTorch provides
+device memory and streams only.
+"""
+from ._binding import (  # noqa: F401
+    ABI_VERSION, LIB_PATH, MODELS, N_FIELDS, SCHEMES, STENCILS, Problem, RDError,
+    checkpoint_count, jvp, lib, n_fields, n_params, set_tile_rows, step, step_batched,
+    vjp, workspace_bytes,
+)

@@ -1,0 +1,352 @@
+// rd_api.cpp -- host runtime behind the C ABI of include/rd.h: argument
+// validation, derived constants, launch geometry, workspace layout and the
+// step loops that enqueue the fused kernels on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "rd_fwd.h"
+#include "rd_host.h"
+
+namespace rd {
+
+static thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(RD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int n_fields(int model) {
+  switch (model) {
+    case RD_MODEL_DIFFUSION: return 1;
+    case RD_MODEL_BARKLEY: return 2;
+    case RD_MODEL_FENTON_KARMA: return 3;
+    case RD_MODEL_BOCF: return 4;
+  }
+  return RD_EINVAL;
+}
+
+int n_params(int model) {
+  switch (model) {
+    case RD_MODEL_DIFFUSION: return 0;
+    case RD_MODEL_BARKLEY: return 3;
+    case RD_MODEL_FENTON_KARMA: return 13;
+    case RD_MODEL_BOCF: return 28;
+  }
+  return RD_EINVAL;
+}
+
+int n_stages(int scheme) {
+  switch (scheme) {
+    case RD_SCHEME_EULER: return 1;
+    case RD_SCHEME_HEUN: return 2;
+    case RD_SCHEME_RK4: return 4;
+  }
+  return RD_EINVAL;
+}
+
+static bool finite(double x) { return std::isfinite(x); }
+
+int validate(const rd_problem* p) {
+  if (!p) return fail(RD_EINVAL, "problem is NULL");
+  if (p->abi_version != RD_ABI_VERSION)
+    return fail(RD_EINVAL, "abi_version %u, library has %d", p->abi_version, RD_ABI_VERSION);
+  if (n_fields(p->model) < 0) return fail(RD_EINVAL, "unknown model %d", p->model);
+  if (n_stages(p->scheme) < 0) return fail(RD_EINVAL, "unknown scheme %d", p->scheme);
+  if (p->stencil != RD_LAP5 && p->stencil != RD_LAP9 && p->stencil != RD_LAP9_ANISO)
+    return fail(RD_EINVAL, "unknown stencil %d", p->stencil);
+  if (p->bc != RD_BC_NOFLUX) return fail(RD_EINVAL, "unknown boundary condition %d", p->bc);
+  if (p->nx < 1 || p->ny < 1) return fail(RD_EINVAL, "grid %d x %d: both sides must be >= 1", p->nx, p->ny);
+  if ((int64_t)p->nx * (int64_t)p->ny >= ((int64_t)1 << 31))
+    return fail(RD_EINVAL, "grid %d x %d has 2^31 cells or more", p->nx, p->ny);
+  if (!(finite(p->dx) && p->dx > 0.0)) return fail(RD_EINVAL, "dx must be finite and > 0");
+  if (!(finite(p->dt) && p->dt > 0.0)) return fail(RD_EINVAL, "dt must be finite and > 0");
+  if (p->nsteps < 0) return fail(RD_EINVAL, "nsteps must be >= 0");
+  if (!(finite(p->D_par) && p->D_par >= 0.0)) return fail(RD_EINVAL, "D_par must be finite and >= 0");
+  if (p->stencil == RD_LAP9_ANISO) {
+    if (!(finite(p->D_perp) && p->D_perp >= 0.0))
+      return fail(RD_EINVAL, "D_perp must be finite and >= 0");
+    if (!finite(p->theta0) || !finite(p->theta1)) return fail(RD_EINVAL, "fibre angles must be finite");
+  }
+  if (!(p->step_k > 0.0)) return fail(RD_EINVAL, "step_k must be > 0 (or +inf)");
+  if (p->nparams != n_params(p->model))
+    return fail(RD_EINVAL, "model %d takes %d parameters, got %d", p->model, n_params(p->model), p->nparams);
+  if (p->nparams > 0 && !p->params) return fail(RD_EINVAL, "params is NULL");
+  for (int i = 0; i < p->nparams; ++i)
+    if (!finite(p->params[i])) return fail(RD_EINVAL, "parameter %d is not finite", i);
+  if (p->checkpoint_every < 0) return fail(RD_EINVAL, "checkpoint_every must be >= 0");
+  return RD_OK;
+}
+
+int validate_fields(const rd_problem* p, double* const* f, const char* what) {
+  if (!f) return fail(RD_EINVAL, "%s array is NULL", what);
+  const int nv = n_fields(p->model);
+  for (int i = 0; i < nv; ++i) {
+    if (!f[i]) return fail(RD_EINVAL, "%s[%d] is NULL", what, i);
+    if (((uintptr_t)f[i]) % 8 != 0) return fail(RD_EINVAL, "%s[%d] is not 8-byte aligned", what, i);
+  }
+  for (int i = 0; i < nv; ++i)
+    for (int j = i + 1; j < nv; ++j)
+      if (f[i] == f[j]) return fail(RD_EINVAL, "%s[%d] and %s[%d] alias", what, i, what, j);
+  return RD_OK;
+}
+
+// Model constants exactly as the equations are written: constant divisors
+// become reciprocals, differences of constants are formed once.
+void derive_constants(const rd_problem* p, KConst& c) {
+  std::memset(&c, 0, sizeof c);
+  c.nx = p->nx;
+  c.ny = p->ny;
+  c.sharp = std::isinf(p->step_k) ? 1 : 0;
+  c.k = c.sharp ? 0.0 : p->step_k;
+  c.dt = p->dt;
+  c.h2 = p->dt * 0.5;
+  c.h6 = p->dt / 6.0;
+  c.cD = p->D_par / (p->dx * p->dx);
+  c.inv_dx2 = 1.0 / (p->dx * p->dx);
+  c.theta0 = p->theta0;
+  c.dtheta = p->theta1 - p->theta0;
+  c.n_total = (double)p->nx;
+  c.d_perp = p->stencil == RD_LAP9_ANISO ? p->D_perp : p->D_par;
+  c.dd = p->D_par - c.d_perp;
+  const double* q = p->params;
+  switch (p->model) {
+    case RD_MODEL_BARKLEY: {
+      BarkleyC& m = c.m.bk;
+      m.b = q[1];
+      m.inv_a = 1.0 / q[0];
+      m.inv_eps = 1.0 / q[2];
+      break;
+    }
+    case RD_MODEL_FENTON_KARMA: {
+      // tau_v+, tau_v1-, tau_v2-, tau_w+, tau_w-, tau_d, tau_0, tau_r, tau_si, k_si, u_csi, u_c, u_v
+      FentonKarmaC& m = c.m.fk;
+      m.inv_tau_vp = 1.0 / q[0];
+      m.tau_v1m = q[1];
+      m.tau_v2m = q[2];
+      m.inv_tau_wp = 1.0 / q[3];
+      m.inv_tau_wm = 1.0 / q[4];
+      m.inv_tau_d = 1.0 / q[5];
+      m.inv_tau_0 = 1.0 / q[6];
+      m.inv_tau_r = 1.0 / q[7];
+      m.inv_2tau_si = 1.0 / (2.0 * q[8]);
+      m.k_si = q[9];
+      m.u_csi = q[10];
+      m.u_c = q[11];
+      m.u_v = q[12];
+      break;
+    }
+    case RD_MODEL_BOCF: {
+      BocfC& m = c.m.bo;
+      m.u_o = q[0];
+      m.u_u = q[1];
+      m.th_v = q[2];
+      m.th_w = q[3];
+      m.th_vm = q[4];
+      m.th_o = q[5];
+      m.tau_v1m = q[6];
+      m.tau_v2m = q[7];
+      m.inv_tau_vp = 1.0 / q[8];
+      m.tau_w1m = q[9];
+      m.dtau_wm = q[10] - q[9];
+      m.k_wm = q[11];
+      m.u_wm = q[12];
+      m.inv_tau_wp = 1.0 / q[13];
+      m.inv_tau_fi = 1.0 / q[14];
+      m.tau_o1 = q[15];
+      m.tau_o2 = q[16];
+      m.tau_so1 = q[17];
+      m.dtau_so = q[18] - q[17];
+      m.k_so = q[19];
+      m.u_so = q[20];
+      m.tau_s1 = q[21];
+      m.tau_s2 = q[22];
+      m.k_s = q[23];
+      m.u_s = q[24];
+      m.inv_tau_si = 1.0 / q[25];
+      m.inv_tau_winf = 1.0 / q[26];
+      m.w_infstar = q[27];
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+// Rows per wave band.  Aims at ~8 waves per compute unit (256 CUs) while
+// keeping bands tall enough that the NS-row ramp at each band end stays cheap.
+static int g_tile_rows_override = -1;
+
+void set_geometry(KConst& c, int ns, int tile_rows) {
+  const int tx = strip_width(ns);
+  c.nsx = (c.nx + tx - 1) / tx;
+  int ty = tile_rows;
+  if (ty <= 0 && g_tile_rows_override > 0) ty = g_tile_rows_override;
+  if (ty <= 0) {
+    const int target_waves = 2048;
+    int nby = std::max(1, (target_waves + c.nsx - 1) / c.nsx);
+    ty = (c.ny + nby - 1) / nby;
+    ty = std::max(ty, 4 * ns);
+  }
+  ty = std::max(1, std::min(ty, c.ny));
+  c.ty = ty;
+  c.nby = (c.ny + ty - 1) / ty;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t field_bytes(const rd_problem* p) {
+  return align_up((size_t)p->nx * (size_t)p->ny * sizeof(double), 256);
+}
+
+hipError_t launch_fwd(int model, int stencil, int scheme, const FwdArgs& a, hipStream_t s) {
+  switch (model) {
+    case RD_MODEL_DIFFUSION: return launch_fwd_diffusion(stencil, scheme, a, s);
+    case RD_MODEL_BARKLEY: return launch_fwd_barkley(stencil, scheme, a, s);
+    case RD_MODEL_FENTON_KARMA: return launch_fwd_fk(stencil, scheme, a, s);
+    case RD_MODEL_BOCF: return launch_fwd_bocf(stencil, scheme, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hipStream_t s) {
+  for (int f = 0; f < nv; ++f) {
+    hipError_t e = hipMemcpyAsync(dst[f], src[f], bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  }
+  return RD_OK;
+}
+
+// nsteps forward steps of the state `a` (in place), ping-ponging through the
+// state-sized buffer `b`; optional checkpoints every `every` steps.
+int forward_steps(const rd_problem* p, const KConst& c, double* const* a, double* const* b,
+                  int64_t nsteps, double* checkpoints, int every, hipStream_t s) {
+  const int nv = n_fields(p->model);
+  const size_t cells = (size_t)p->nx * (size_t)p->ny;
+  const size_t bytes = cells * sizeof(double);
+  double* bufA[kMaxFields];
+  double* bufB[kMaxFields];
+  for (int f = 0; f < nv; ++f) {
+    bufA[f] = a[f];
+    bufB[f] = b[f];
+  }
+  double** cur = bufA;
+  double** oth = bufB;
+  if (nsteps % 2 == 1) {
+    int rc = copy_state(bufB, bufA, nv, bytes, s);
+    if (rc) return rc;
+    cur = bufB;
+    oth = bufA;
+  }
+  FwdArgs args;
+  std::memset(&args, 0, sizeof args);
+  args.c = c;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    if (checkpoints && every > 0 && n % every == 0) {
+      double* dst[kMaxFields];
+      for (int f = 0; f < nv; ++f) dst[f] = checkpoints + ((size_t)(n / every) * nv + f) * cells;
+      int rc = copy_state(dst, cur, nv, bytes, s);
+      if (rc) return rc;
+    }
+    for (int f = 0; f < nv; ++f) {
+      args.in[f] = cur[f];
+      args.out[f] = oth[f];
+    }
+    hipError_t e = launch_fwd(p->model, p->stencil, p->scheme, args, s);
+    if (e != hipSuccess) return hip_fail(e, "forward step launch");
+    std::swap(cur, oth);
+  }
+  return RD_OK;
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" {
+
+int rd_abi_version(void) { return RD_ABI_VERSION; }
+
+int rd_n_fields(int32_t model) {
+  int n = n_fields(model);
+  if (n < 0) return fail(RD_EINVAL, "unknown model %d", model);
+  return n;
+}
+
+int rd_n_params(int32_t model) {
+  int n = n_params(model);
+  if (n < 0) return fail(RD_EINVAL, "unknown model %d", model);
+  return n;
+}
+
+const char* rd_last_error(void) { return g_error.c_str(); }
+
+int rd_checkpoint_count(const rd_problem* p, int64_t* out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return fail(RD_EINVAL, "out is NULL");
+  *out = p->checkpoint_every > 0 ? (p->nsteps + p->checkpoint_every - 1) / p->checkpoint_every : 0;
+  return RD_OK;
+}
+
+int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return fail(RD_EINVAL, "out is NULL");
+  const size_t nv = (size_t)n_fields(p->model);
+  const size_t fb = field_bytes(p);
+  switch (op) {
+    case RD_OP_STEP: *out = nv * fb; return RD_OK;
+    case RD_OP_JVP: return workspace_jvp(p, out);
+    case RD_OP_VJP: return workspace_vjp(p, out);
+    case RD_OP_BATCHED:
+      return fail(RD_EINVAL, "use rd_step_batched_workspace_bytes for batched runs");
+  }
+  return fail(RD_EINVAL, "unknown op %d", op);
+}
+
+int rd_step(const rd_problem* p, double* const* fields, double* checkpoints, void* ws,
+            size_t ws_bytes, void* hip_stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = validate_fields(p, fields, "fields");
+  if (rc) return rc;
+  if (checkpoints && ((uintptr_t)checkpoints) % 8 != 0)
+    return fail(RD_EINVAL, "checkpoints is not 8-byte aligned");
+  size_t need = 0;
+  rd_workspace_bytes(p, RD_OP_STEP, &need);
+  if (p->nsteps == 0) return RD_OK;
+  if (!ws || ws_bytes < need)
+    return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+  if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
+  const int nv = n_fields(p->model);
+  double* b[kMaxFields];
+  for (int f = 0; f < nv; ++f) b[f] = (double*)((char*)ws + f * field_bytes(p));
+  KConst c;
+  derive_constants(p, c);
+  set_geometry(c, n_stages(p->scheme), -1);
+  return forward_steps(p, c, fields, b, p->nsteps, checkpoints, p->checkpoint_every,
+                       (hipStream_t)hip_stream);
+}
+
+// Sets the rows per wave band used by later calls (0 or less: automatic).
+// A tuning knob for measurements; results do not depend on it.
+int rd_set_tile_rows(int32_t rows) {
+  g_tile_rows_override = rows;
+  return RD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// rd_device.h -- device-side building blocks of the explicit reaction-diffusion
+// step (Marcotte & Grigoriev, arXiv:1309.1720): kernel constants, the smoothed
+// step H_k (Sect. 2), the reaction terms N[z] of Eq. (1), their pointwise
+// Jacobians, and the diffusion operators (Eq. 6 and the anisotropic flux form)
+// evaluated across a wavefront whose 64 lanes hold 64 consecutive columns.
+//
+// All arithmetic is FP64.  Sources are built with -ffp-contract=off so that
+// every product and sum rounds where the source writes it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rd.h"
+
+namespace rd {
+
+constexpr int kMaxFields = 4;
+constexpr int kWave = 64;
+constexpr double kAlphaAxial = 2.0 / 3.0;  // Eq. (6) axial weight
+constexpr double kAlphaDiag = 1.0 / 6.0;   // Eq. (6) diagonal weight
+
+// Model constants, derived on the host from the caller's parameters.  Constant
+// divisors are stored as reciprocals; u-dependent time constants are divided.
+struct BarkleyC { double b, inv_a, inv_eps; };
+struct FentonKarmaC {
+  double u_c, u_v, inv_tau_d, inv_tau_0, inv_tau_r, inv_2tau_si, k_si, u_csi,
+      tau_v1m, tau_v2m, inv_tau_vp, inv_tau_wm, inv_tau_wp;
+};
+struct BocfC {
+  double u_o, u_u, th_v, th_w, th_vm, th_o, tau_v1m, tau_v2m, inv_tau_vp, tau_w1m,
+      dtau_wm, k_wm, u_wm, inv_tau_wp, inv_tau_fi, tau_o1, tau_o2, tau_so1, dtau_so,
+      k_so, u_so, tau_s1, tau_s2, k_s, u_s, inv_tau_si, inv_tau_winf, w_infstar;
+};
+union ModelC {
+  BarkleyC bk;
+  FentonKarmaC fk;
+  BocfC bo;
+  double raw[32];
+};
+
+// Everything a step kernel needs besides field pointers (passed by value).
+struct KConst {
+  int nx, ny;        // grid
+  int nsx, nby, ty;  // launch geometry: column strips, row bands, rows per band
+  int sharp;         // 1: Heaviside step instead of H_k
+  double k;          // H_k sharpness
+  double dt, h2, h6; // dt, dt/2, dt/6
+  double cD;         // D_par / dx^2 (isotropic stencils)
+  double inv_dx2;    // 1 / dx^2 (anisotropic flux form)
+  double theta0, dtheta, n_total, d_perp, dd;  // fibre field, dd = D_par - D_perp
+  ModelC m;
+};
+
+template <int MODEL> struct ModelTraits;
+template <> struct ModelTraits<RD_MODEL_DIFFUSION> { static constexpr int NV = 1; };
+template <> struct ModelTraits<RD_MODEL_BARKLEY> { static constexpr int NV = 2; };
+template <> struct ModelTraits<RD_MODEL_FENTON_KARMA> { static constexpr int NV = 3; };
+template <> struct ModelTraits<RD_MODEL_BOCF> { static constexpr int NV = 4; };
+
+// ---------------------------------------------------------------------------
+// Smoothed step: t = kx + 1/2 clamped to [0, 1], H = t^2 (3 - 2t).  Clamping
+// reproduces the 0 and 1 branches exactly (0*0*3 = 0, 1*1*1 = 1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double step_h(double x, const KConst& c) {
+  if (c.sharp) return x >= 0.0 ? 1.0 : 0.0;
+  double t = c.k * x + 0.5;
+  t = fmin(fmax(t, 0.0), 1.0);
+  return t * t * (3.0 - 2.0 * t);
+}
+
+// H and dH/dx = 6 k t (1 - t) (zero outside the transition and for Heaviside).
+__device__ __forceinline__ void step_h_d(double x, const KConst& c, double& h, double& dh) {
+  if (c.sharp) {
+    h = x >= 0.0 ? 1.0 : 0.0;
+    dh = 0.0;
+    return;
+  }
+  double t = c.k * x + 0.5;
+  t = fmin(fmax(t, 0.0), 1.0);
+  h = t * t * (3.0 - 2.0 * t);
+  dh = ((6.0 * c.k) * t) * (1.0 - t);
+}
+
+// ---------------------------------------------------------------------------
+// Reaction rates f = N(y).
+// ---------------------------------------------------------------------------
+template <int MODEL> struct Reaction;
+
+template <> struct Reaction<RD_MODEL_DIFFUSION> {
+  __device__ __forceinline__ static void rates(const KConst&, const double*, double* f) {
+    f[0] = 0.0;
+  }
+};
+
+// Barkley: du = (1/eps) u (1 - u)(u - (v + b)/a), dv = u - v.
+template <> struct Reaction<RD_MODEL_BARKLEY> {
+  __device__ __forceinline__ static void rates(const KConst& c, const double* y, double* f) {
+    const BarkleyC& m = c.m.bk;
+    const double u = y[0], v = y[1];
+    const double uth = (v + m.b) * m.inv_a;
+    f[0] = ((m.inv_eps * u) * (1.0 - u)) * (u - uth);
+    f[1] = u - v;
+  }
+};
+
+// Fenton-Karma three-variable model, gates through H_k:
+// J_fi = -v p (1-u)(u-u_c)/tau_d, J_so = u(1-p)/tau_0 + p/tau_r,
+// J_si = -w (1 + tanh(k_si (u - u_csi))) / (2 tau_si),
+// dv = (1-p)(1-v)/tau_v^-(u) - p v/tau_v^+, dw = (1-p)(1-w)/tau_w^- - p w/tau_w^+.
+template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
+  __device__ __forceinline__ static void rates(const KConst& c, const double* y, double* f) {
+    const FentonKarmaC& m = c.m.fk;
+    const double u = y[0], v = y[1], w = y[2];
+    const double p = step_h(u - m.u_c, c);
+    const double q = step_h(u - m.u_v, c);
+    const double j_fi = -(((v * p) * (1.0 - u)) * (u - m.u_c)) * m.inv_tau_d;
+    const double j_so = (u * (1.0 - p)) * m.inv_tau_0 + p * m.inv_tau_r;
+    const double j_si = -(w * (1.0 + tanh(m.k_si * (u - m.u_csi)))) * m.inv_2tau_si;
+    const double tau_vm = q * m.tau_v1m + (1.0 - q) * m.tau_v2m;
+    f[0] = -((j_fi + j_so) + j_si);
+    f[1] = ((1.0 - p) * (1.0 - v)) / tau_vm - (p * v) * m.inv_tau_vp;
+    f[2] = ((1.0 - p) * (1.0 - w)) * m.inv_tau_wm - (p * w) * m.inv_tau_wp;
+  }
+};
+
+// Bueno-Orovio four-variable model, Eq. (5) with the currents and the
+// alpha/beta gate form; tau(u), v_inf, w_inf as in Bueno-Orovio et al. (2008).
+template <> struct Reaction<RD_MODEL_BOCF> {
+  __device__ __forceinline__ static void rates(const KConst& c, const double* y, double* f) {
+    const BocfC& m = c.m.bo;
+    const double u = y[0], v = y[1], w = y[2], s = y[3];
+    const double h_v = step_h(u - m.th_v, c);
+    const double h_v_neg = step_h(m.th_v - u, c);
+    const double h_w = step_h(u - m.th_w, c);
+    const double h_w_neg = step_h(m.th_w - u, c);
+    const double h_vm = step_h(u - m.th_vm, c);
+    const double h_o = step_h(u - m.th_o, c);
+    const double tau_vm = (1.0 - h_vm) * m.tau_v1m + h_vm * m.tau_v2m;
+    const double tau_wm = m.tau_w1m + m.dtau_wm * ((1.0 + tanh(m.k_wm * (u - m.u_wm))) * 0.5);
+    const double tau_so = m.tau_so1 + m.dtau_so * ((1.0 + tanh(m.k_so * (u - m.u_so))) * 0.5);
+    const double tau_s = (1.0 - h_w) * m.tau_s1 + h_w * m.tau_s2;
+    const double tau_o = (1.0 - h_o) * m.tau_o1 + h_o * m.tau_o2;
+    const double v_inf = step_h(m.th_vm - u, c);
+    const double w_inf = (1.0 - h_o) * (1.0 - u * m.inv_tau_winf) + h_o * m.w_infstar;
+    const double j_fi = -(((v * h_v) * (u - m.th_v)) * (m.u_u - u)) * m.inv_tau_fi;
+    const double j_so = ((u - m.u_o) * h_w_neg) / tau_o + h_w / tau_so;
+    const double j_si = -((h_w * w) * s) * m.inv_tau_si;
+    f[0] = -((j_fi + j_so) + j_si);
+    const double alpha_v = -(h_v * m.inv_tau_vp) - h_v_neg / tau_vm;
+    const double beta_v = (h_v_neg * v_inf) / tau_vm;
+    f[1] = alpha_v * v + beta_v;
+    const double alpha_w = -(h_w * m.inv_tau_wp) - h_w_neg / tau_wm;
+    const double beta_w = (h_w_neg * w_inf) / tau_wm;
+    f[2] = alpha_w * w + beta_w;
+    f[3] = ((1.0 + tanh(m.k_s * (u - m.u_s))) * 0.5 - s) / tau_s;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Cross-lane access.  Lane l holds column x0 + l; the previous/next lane holds
+// the west/east neighbour.  Lanes 0 and 63 read their own value (they are halo
+// lanes whose results never reach an output).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double from_west(double v) { return __shfl_up(v, 1, kWave); }
+__device__ __forceinline__ double from_east(double v) { return __shfl_down(v, 1, kWave); }
+
+// Per-lane geometry of a column.
+struct Column {
+  int gx;        // global column of this lane (may lie outside [0, nx))
+  bool west;     // gx <= 0: west neighbour is the mirror ghost (this column)
+  bool east;     // gx >= nx-1: east neighbour is the mirror ghost
+  double dxx_e, dxy_e4, dxy_c4, dyy_c;  // anisotropic tensor at face gx+1/2 / centre gx
+};
+
+__device__ __forceinline__ Column make_column(int gx, const KConst& c, bool aniso) {
+  Column col;
+  col.gx = gx;
+  col.west = gx <= 0;
+  col.east = gx >= c.nx - 1;
+  col.dxx_e = col.dxy_e4 = col.dxy_c4 = col.dyy_c = 0.0;
+  if (aniso) {
+    const double g = (double)gx;
+    const double th_f = c.theta0 + c.dtheta * ((g + 1.0) / c.n_total);
+    const double th_c = c.theta0 + c.dtheta * ((g + 0.5) / c.n_total);
+    const double cf = cos(th_f), sf = sin(th_f), cc = cos(th_c), sc = sin(th_c);
+    col.dxx_e = c.d_perp + (c.dd * cf) * cf;
+    col.dxy_e4 = 0.25 * ((c.dd * cf) * sf);
+    col.dxy_c4 = 0.25 * ((c.dd * cc) * sc);
+    col.dyy_c = c.d_perp + (c.dd * sc) * sc;
+  }
+  return col;
+}
+
+// Diffusion term at row `rho` of this lane's column, given the values `up`
+// (row rho-1), `cen` (row rho) and `dn` (row rho+1), already mirrored in y
+// (up = cen at rho = 0, dn = cen at rho = ny-1).  All lanes of the wave must
+// call it together (cross-lane reads).
+template <int STENCIL>
+__device__ __forceinline__ double diffusion(double up, double cen, double dn, const Column& col,
+                                            int rho, const KConst& c) {
+  if constexpr (STENCIL == RD_LAP5) {
+    double w = from_west(cen), e = from_east(cen);
+    if (col.west) w = cen;
+    if (col.east) e = cen;
+    return c.cD * (((w + e) + (up + dn)) - 4.0 * cen);
+  } else if constexpr (STENCIL == RD_LAP9) {
+    const double cs = up + dn;  // N + S of this column
+    double w = from_west(cen), e = from_east(cen);
+    double ws = from_west(cs), es = from_east(cs);  // NW + SW, NE + SE
+    if (col.west) { w = cen; ws = cs; }
+    if (col.east) { e = cen; es = cs; }
+    const double axial = ((w + e) + cs) - 4.0 * cen;
+    const double diag = (ws + es) - 4.0 * cen;
+    return c.cD * (kAlphaAxial * axial + kAlphaDiag * diag);
+  } else {
+    // Conservative flux form: x-face fluxes shared with the west neighbour
+    // through a lane shuffle, y-face fluxes recomputed by both rows with the
+    // same operands; zero flux through boundary faces.
+    const double wC = from_west(cen), eC = from_east(cen);
+    const double wU = from_west(up), eU = from_east(up);
+    const double wD = from_west(dn), eD = from_east(dn);
+    double fxe = col.dxx_e * (eC - cen) + col.dxy_e4 * ((eD + dn) - (eU + up));
+    if (col.east) fxe = 0.0;
+    double fxw = from_west(fxe);
+    if (col.west) fxw = 0.0;
+    const double wCc = col.west ? cen : wC, eCc = col.east ? cen : eC;
+    const double wUc = col.west ? up : wU, eUc = col.east ? up : eU;
+    const double wDc = col.west ? dn : wD, eDc = col.east ? dn : eD;
+    double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (dn - cen);
+    double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (cen - up);
+    if (rho == c.ny - 1) fys = 0.0;
+    if (rho == 0) fyn = 0.0;
+    return ((fxe - fxw) + (fys - fyn)) * c.inv_dx2;
+  }
+}
+
+}  // namespace rd

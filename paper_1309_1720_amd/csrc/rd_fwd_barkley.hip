@@ -1,0 +1,8 @@
+// Forward fused-step kernels of the barkley model (all stencils and schemes).
+#include "rd_fwd.h"
+
+namespace rd {
+hipError_t launch_fwd_barkley(int stencil, int scheme, const FwdArgs& a, hipStream_t stream) {
+  return launch_fwd_model<RD_MODEL_BARKLEY>(stencil, scheme, a, stream);
+}
+}  // namespace rd

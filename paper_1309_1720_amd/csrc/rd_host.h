@@ -1,0 +1,24 @@
+// rd_host.h -- host-side helpers shared by the C ABI implementation files.
+#pragma once
+
+#include "rd_device.h"
+
+namespace rd {
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int n_fields(int model);
+int n_params(int model);
+int n_stages(int scheme);
+int validate(const rd_problem* p);
+int validate_fields(const rd_problem* p, double* const* f, const char* what);
+void derive_constants(const rd_problem* p, KConst& c);
+void set_geometry(KConst& c, int ns, int tile_rows);
+size_t align_up(size_t x, size_t a);
+size_t field_bytes(const rd_problem* p);
+int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hipStream_t s);
+
+int workspace_jvp(const rd_problem* p, size_t* out);
+int workspace_vjp(const rd_problem* p, size_t* out);
+
+}  // namespace rd
