@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 FP64_VECTOR_PEAK = 78.6e12  # flop/s, MI355X FP64 vector (FMA = 2 flops)
-KERNEL_SOURCES = ["paper_1309_1720_amd/csrc/rd_device.h", "paper_1309_1720_amd/csrc/rd_fwd.h"]
+KERNEL_SOURCES = ["paper_1309_1720_amd/csrc/rd_device.h", "paper_1309_1720_amd/csrc/rd_sweep.h"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "fwd_fk_1024_rk4_counters.json")
 
 
@@ -69,6 +69,49 @@ def cpu_baseline(w, params, seconds: float):
                       f"(NumPy, single thread), {el:.1f} s"}
 
 
+def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
+    """Exact tangent-linear JVP (rd_jvp) against central finite differences of
+    two forward runs, on the same grid: cost per step and accuracy."""
+    import numpy as np
+    import rd_inputs as ri
+    nx, ny = w["nx"], w["ny"]
+    v_np = ri.direction(3, nx, ny, 4100)
+    stream = torch.cuda.current_stream(dev)
+    # cost: jvp steps timed like the forward
+    z = [torch.from_numpy(a).to(dev) for a in z0_np]
+    v = [torch.from_numpy(a).to(dev) for a in v_np]
+    p = rd.Problem.from_workload(w, params, nsteps=20)
+    rd.jvp(p, z, v)
+    p.nsteps = steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    rd.jvp(p, z, v)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    jvp_ms = e0.elapsed_time(e1) / steps
+    # accuracy over a short horizon: FD error relative to the exact JVP
+    horizon = 100
+    p = rd.Problem.from_workload(w, params, nsteps=horizon)
+    z = [torch.from_numpy(a).to(dev) for a in z0_np]
+    v = [torch.from_numpy(a).to(dev) for a in v_np]
+    rd.jvp(p, z, v)
+    jv = torch.cat([t.flatten() for t in v])
+    errs = {}
+    for k in range(9, 4, -1):
+        eps = 10.0 ** (-k)
+        zp = [torch.from_numpy(a + eps * b).to(dev) for a, b in zip(z0_np, v_np)]
+        zm = [torch.from_numpy(a - eps * b).to(dev) for a, b in zip(z0_np, v_np)]
+        rd.step(p, zp)
+        rd.step(p, zm)
+        fd = (torch.cat([t.flatten() for t in zp]) - torch.cat([t.flatten() for t in zm])) / (2 * eps)
+        errs[f"{eps:.0e}"] = float(torch.linalg.norm(fd - jv) / torch.linalg.norm(jv))
+    return {"ms_per_step": jvp_ms, "over_forward": jvp_ms / fwd_ms,
+            "fd_jvp_ms_per_step": 2 * fwd_ms, "fd_rel_err_by_eps": errs,
+            "fd_best_rel_err": min(errs.values()), "horizon_steps": horizon,
+            "timed_steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +120,7 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-jvp", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -94,7 +138,8 @@ def main():
     nv = ri.N_FIELDS["fk"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    z0_np = ri.initial_condition(w)
+    z = [torch.from_numpy(a).to(dev) for a in z0_np]
     if args.tile_rows:
         rd.set_tile_rows(args.tile_rows)
     p = rd.Problem.from_workload(w, params, nsteps=args.warmup)
@@ -144,6 +189,9 @@ def main():
                      "avg_launch_us": launch_s * 1e6},
         "wall_s": wall,
     }
+    if not args.no_jvp:
+        out["jvp"] = jvp_report(rd, torch, w, params, z0_np, ms / args.steps,
+                                min(args.steps, 1000), dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, params, args.cpu_seconds)
     print(json.dumps(out), flush=True)

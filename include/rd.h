@@ -186,6 +186,14 @@ int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* cons
  * automatic choice).  A performance knob: results do not depend on it. */
 int rd_set_tile_rows(int32_t rows);
 
+/* Enables (non-zero, the default) or disables the band-height autotuner.
+ * When enabled, the first call for each (operation, model, stencil, scheme,
+ * nx, ny) times candidate band heights with HIP events on the caller's stream
+ * (trial launches read the inputs and write only workspace) and blocks until
+ * those timings finish; later calls reuse the choice.  Never inside a stream
+ * capture.  Results do not depend on it. */
+int rd_set_autotune(int32_t enable);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* rd_last_error(void);
 

@@ -71,6 +71,7 @@ def lib() -> C.CDLL:
             "rd_step_batched_workspace_bytes": ([P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
             "rd_step_batched": ([P, C.c_int32, C.POINTER(_DPP), C.POINTER(_DPP), _PTR, C.c_size_t, _PTR], C.c_int),
             "rd_set_tile_rows": ([C.c_int32], C.c_int),
+            "rd_set_autotune": ([C.c_int32], C.c_int),
             "rd_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -186,6 +187,11 @@ def checkpoint_count(prob: Problem) -> int:
 def set_tile_rows(rows: int) -> None:
     """Rows per wavefront band for later calls (<= 0: automatic)."""
     _check(lib().rd_set_tile_rows(int(rows)))
+
+
+def set_autotune(enable: bool) -> None:
+    """Enable or disable the band-height autotuner (see rd_set_autotune)."""
+    _check(lib().rd_set_autotune(1 if enable else 0))
 
 
 def step(prob: Problem, fields, checkpoints: torch.Tensor | None = None):

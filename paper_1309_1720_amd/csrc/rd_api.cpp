@@ -8,7 +8,7 @@
 #include <cstring>
 #include <string>
 
-#include "rd_fwd.h"
+#include "rd_sweep.h"
 #include "rd_host.h"
 
 namespace rd {
@@ -186,21 +186,11 @@ void derive_constants(const rd_problem* p, KConst& c) {
   }
 }
 
-// Rows per wave band.  Aims at ~8 waves per compute unit (256 CUs) while
-// keeping bands tall enough that the NS-row ramp at each band end stays cheap.
-static int g_tile_rows_override = -1;
-
-void set_geometry(KConst& c, int ns, int tile_rows) {
+// Launch geometry for `ty` rows per wave band: column strips of 64 - 2 ns
+// outputs, bands of ty rows.
+void set_geometry(KConst& c, int ns, int ty) {
   const int tx = strip_width(ns);
   c.nsx = (c.nx + tx - 1) / tx;
-  int ty = tile_rows;
-  if (ty <= 0 && g_tile_rows_override > 0) ty = g_tile_rows_override;
-  if (ty <= 0) {
-    const int target_waves = 2048;
-    int nby = std::max(1, (target_waves + c.nsx - 1) / c.nsx);
-    ty = (c.ny + nby - 1) / nby;
-    ty = std::max(ty, 4 * ns);
-  }
   ty = std::max(1, std::min(ty, c.ny));
   c.ty = ty;
   c.nby = (c.ny + ty - 1) / ty;
@@ -212,12 +202,19 @@ size_t field_bytes(const rd_problem* p) {
   return align_up((size_t)p->nx * (size_t)p->ny * sizeof(double), 256);
 }
 
-hipError_t launch_fwd(int model, int stencil, int scheme, const FwdArgs& a, hipStream_t s) {
+hipError_t launch_step_kernel(bool tangent, int model, int stencil, int scheme, const SweepArgs& a,
+                              hipStream_t s) {
   switch (model) {
-    case RD_MODEL_DIFFUSION: return launch_fwd_diffusion(stencil, scheme, a, s);
-    case RD_MODEL_BARKLEY: return launch_fwd_barkley(stencil, scheme, a, s);
-    case RD_MODEL_FENTON_KARMA: return launch_fwd_fk(stencil, scheme, a, s);
-    case RD_MODEL_BOCF: return launch_fwd_bocf(stencil, scheme, a, s);
+    case RD_MODEL_DIFFUSION:
+      return tangent ? launch_sweep_tan_diffusion(stencil, scheme, a, s)
+                     : launch_sweep_fwd_diffusion(stencil, scheme, a, s);
+    case RD_MODEL_BARKLEY:
+      return tangent ? launch_sweep_tan_barkley(stencil, scheme, a, s)
+                     : launch_sweep_fwd_barkley(stencil, scheme, a, s);
+    case RD_MODEL_FENTON_KARMA:
+      return tangent ? launch_sweep_tan_fk(stencil, scheme, a, s) : launch_sweep_fwd_fk(stencil, scheme, a, s);
+    case RD_MODEL_BOCF:
+      return tangent ? launch_sweep_tan_bocf(stencil, scheme, a, s) : launch_sweep_fwd_bocf(stencil, scheme, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -230,28 +227,30 @@ int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hip
   return RD_OK;
 }
 
-// nsteps forward steps of the state `a` (in place), ping-ponging through the
-// state-sized buffer `b`; optional checkpoints every `every` steps.
-int forward_steps(const rd_problem* p, const KConst& c, double* const* a, double* const* b,
-                  int64_t nsteps, double* checkpoints, int every, hipStream_t s) {
+// nsteps fused steps of the packed arrays `a` (np = NV state fields, or 2 NV
+// with the tangent fields after them), in place, ping-ponging through the
+// equally sized buffers `b`; optional state checkpoints every `every` steps.
+int run_steps(const rd_problem* p, const KConst& c, bool tangent, double* const* a,
+              double* const* b, int64_t nsteps, double* checkpoints, int every, hipStream_t s) {
   const int nv = n_fields(p->model);
+  const int np = tangent ? 2 * nv : nv;
   const size_t cells = (size_t)p->nx * (size_t)p->ny;
   const size_t bytes = cells * sizeof(double);
-  double* bufA[kMaxFields];
-  double* bufB[kMaxFields];
-  for (int f = 0; f < nv; ++f) {
+  double* bufA[kMaxPacked];
+  double* bufB[kMaxPacked];
+  for (int f = 0; f < np; ++f) {
     bufA[f] = a[f];
     bufB[f] = b[f];
   }
   double** cur = bufA;
   double** oth = bufB;
   if (nsteps % 2 == 1) {
-    int rc = copy_state(bufB, bufA, nv, bytes, s);
+    int rc = copy_state(bufB, bufA, np, bytes, s);
     if (rc) return rc;
     cur = bufB;
     oth = bufA;
   }
-  FwdArgs args;
+  SweepArgs args;
   std::memset(&args, 0, sizeof args);
   args.c = c;
   for (int64_t n = 0; n < nsteps; ++n) {
@@ -261,14 +260,49 @@ int forward_steps(const rd_problem* p, const KConst& c, double* const* a, double
       int rc = copy_state(dst, cur, nv, bytes, s);
       if (rc) return rc;
     }
-    for (int f = 0; f < nv; ++f) {
+    for (int f = 0; f < np; ++f) {
       args.in[f] = cur[f];
       args.out[f] = oth[f];
     }
-    hipError_t e = launch_fwd(p->model, p->stencil, p->scheme, args, s);
-    if (e != hipSuccess) return hip_fail(e, "forward step launch");
+    hipError_t e = launch_step_kernel(tangent, p->model, p->stencil, p->scheme, args, s);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     std::swap(cur, oth);
   }
+  return RD_OK;
+}
+
+// Chooses the band height for (problem, mode) -- tuning on first use with
+// trial launches from `in` into `out` -- and stores the geometry in `c`.
+void plan_geometry(const rd_problem* p, KConst& c, bool tangent, double* const* in,
+                   double* const* out, hipStream_t s) {
+  const int ns = n_stages(p->scheme);
+  const int np = (tangent ? 2 : 1) * n_fields(p->model);
+  auto trial = [&](int ty) {
+    SweepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.c = c;
+    set_geometry(a.c, ns, ty);
+    for (int f = 0; f < np; ++f) {
+      a.in[f] = in[f];
+      a.out[f] = out[f];
+    }
+    return launch_step_kernel(tangent, p->model, p->stencil, p->scheme, a, s);
+  };
+  const int ty = tuned_rows(tangent ? kTuneTangent : kTuneForward, p->model, p->stencil, p->scheme,
+                            p->nx, p->ny, ns, s, trial);
+  set_geometry(c, ns, ty);
+}
+
+int check_workspace(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return RD_OK;
+  if (!ws || ws_bytes < need)
+    return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+  if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
+  return RD_OK;
+}
+
+int workspace_jvp(const rd_problem* p, size_t* out) {
+  *out = 2 * (size_t)n_fields(p->model) * field_bytes(p);
   return RD_OK;
 }
 
@@ -326,27 +360,50 @@ int rd_step(const rd_problem* p, double* const* fields, double* checkpoints, voi
   if (rc) return rc;
   if (checkpoints && ((uintptr_t)checkpoints) % 8 != 0)
     return fail(RD_EINVAL, "checkpoints is not 8-byte aligned");
+  if (p->nsteps == 0) return RD_OK;
   size_t need = 0;
   rd_workspace_bytes(p, RD_OP_STEP, &need);
-  if (p->nsteps == 0) return RD_OK;
-  if (!ws || ws_bytes < need)
-    return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
-  if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
+  rc = check_workspace(ws, ws_bytes, need);
+  if (rc) return rc;
   const int nv = n_fields(p->model);
   double* b[kMaxFields];
   for (int f = 0; f < nv; ++f) b[f] = (double*)((char*)ws + f * field_bytes(p));
+  hipStream_t s = (hipStream_t)hip_stream;
   KConst c;
   derive_constants(p, c);
-  set_geometry(c, n_stages(p->scheme), -1);
-  return forward_steps(p, c, fields, b, p->nsteps, checkpoints, p->checkpoint_every,
-                       (hipStream_t)hip_stream);
+  plan_geometry(p, c, false, fields, b, s);
+  return run_steps(p, c, false, fields, b, p->nsteps, checkpoints, p->checkpoint_every, s);
 }
 
-// Sets the rows per wave band used by later calls (0 or less: automatic).
-// A tuning knob for measurements; results do not depend on it.
-int rd_set_tile_rows(int32_t rows) {
-  g_tile_rows_override = rows;
-  return RD_OK;
+int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents, void* ws,
+           size_t ws_bytes, void* hip_stream) {
+  int rc = validate(p);
+  if (rc) return rc;
+  rc = validate_fields(p, fields, "fields");
+  if (rc) return rc;
+  rc = validate_fields(p, tangents, "tangents");
+  if (rc) return rc;
+  const int nv = n_fields(p->model);
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j < nv; ++j)
+      if (fields[i] == tangents[j]) return fail(RD_EINVAL, "fields[%d] aliases tangents[%d]", i, j);
+  if (p->nsteps == 0) return RD_OK;
+  size_t need = 0;
+  workspace_jvp(p, &need);
+  rc = check_workspace(ws, ws_bytes, need);
+  if (rc) return rc;
+  double* a[kMaxPacked];
+  double* b[kMaxPacked];
+  for (int f = 0; f < nv; ++f) {
+    a[f] = fields[f];
+    a[nv + f] = tangents[f];
+  }
+  for (int f = 0; f < 2 * nv; ++f) b[f] = (double*)((char*)ws + f * field_bytes(p));
+  hipStream_t s = (hipStream_t)hip_stream;
+  KConst c;
+  derive_constants(p, c);
+  plan_geometry(p, c, true, a, b, s);
+  return run_steps(p, c, true, a, b, p->nsteps, nullptr, 0, s);
 }
 
 }  // extern "C"

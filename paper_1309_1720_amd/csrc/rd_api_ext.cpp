@@ -2,10 +2,6 @@
 #include "rd_host.h"
 
 namespace rd {
-int workspace_jvp(const rd_problem* p, size_t* out) {
-  *out = 2 * (size_t)n_fields(p->model) * field_bytes(p);
-  return RD_OK;
-}
 int workspace_vjp(const rd_problem* p, size_t* out) {
   *out = 0;
   return fail(RD_EUNSUPPORTED, "rd_vjp is not available in this build");
@@ -14,11 +10,6 @@ int workspace_vjp(const rd_problem* p, size_t* out) {
 
 using namespace rd;
 extern "C" {
-int rd_jvp(const rd_problem* p, double* const*, double* const*, void*, size_t, void*) {
-  int rc = validate(p);
-  if (rc) return rc;
-  return fail(RD_EUNSUPPORTED, "rd_jvp is not available in this build");
-}
 int rd_vjp(const rd_problem* p, const double*, double* const*, void*, size_t, void*) {
   int rc = validate(p);
   if (rc) return rc;

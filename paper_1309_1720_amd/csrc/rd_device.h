@@ -83,22 +83,76 @@ __device__ __forceinline__ void step_h_d(double x, const KConst& c, double& h, d
 }
 
 // ---------------------------------------------------------------------------
-// Reaction rates f = N(y).
+// Forward-mode dual numbers: a value and one directional derivative.  The
+// reaction code is written once over a scalar type T; instantiated with Dual
+// it returns N(y) and J_N(y) dy together.  Each operation computes its value
+// exactly as the double version does, so the value parts are bit-identical
+// to a plain evaluation.
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual() = default;
+  __host__ __device__ explicit constexpr Dual(double x) : v(x), d(0.0) {}
+  __host__ __device__ constexpr Dual(double x, double dx) : v(x), d(dx) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+__device__ __forceinline__ Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+__device__ __forceinline__ Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ Dual operator/(double a, Dual b) {
+  const double q = a / b.v;
+  return Dual(q, -(q * b.d) / b.v);
+}
+__device__ __forceinline__ Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+__device__ __forceinline__ double exp(double a) { return ::exp(a); }
+__device__ __forceinline__ Dual exp(Dual a) {
+  const double e = ::exp(a.v);
+  return Dual(e, e * a.d);
+}
+__device__ __forceinline__ Dual step_h(Dual x, const KConst& c) {
+  double h, dh;
+  step_h_d(x.v, c, h, dh);
+  return Dual(h, dh * x.d);
+}
+
+// (1 + tanh(x)) / 2 written as the logistic function 1 / (1 + exp(-2x)): the
+// same function, evaluated with one exp and one division (an FP64 tanh costs
+// several times more), and without the cancellation 1 + tanh(x) suffers for
+// x << 0.
+template <class T>
+__device__ __forceinline__ T half_one_plus_tanh(T x) {
+  return 1.0 / (1.0 + exp(-2.0 * x));
+}
+
+// ---------------------------------------------------------------------------
+// Reaction rates f = N(y), every operation rounded as written.
 // ---------------------------------------------------------------------------
 template <int MODEL> struct Reaction;
 
 template <> struct Reaction<RD_MODEL_DIFFUSION> {
-  __device__ __forceinline__ static void rates(const KConst&, const double*, double* f) {
-    f[0] = 0.0;
+  template <class T>
+  __device__ __forceinline__ static void rates(const KConst&, const T*, T* f) {
+    f[0] = T(0.0);
   }
 };
 
 // Barkley: du = (1/eps) u (1 - u)(u - (v + b)/a), dv = u - v.
 template <> struct Reaction<RD_MODEL_BARKLEY> {
-  __device__ __forceinline__ static void rates(const KConst& c, const double* y, double* f) {
+  template <class T>
+  __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const BarkleyC& m = c.m.bk;
-    const double u = y[0], v = y[1];
-    const double uth = (v + m.b) * m.inv_a;
+    const T u = y[0], v = y[1];
+    const T uth = (v + m.b) * m.inv_a;
     f[0] = ((m.inv_eps * u) * (1.0 - u)) * (u - uth);
     f[1] = u - v;
   }
@@ -109,15 +163,16 @@ template <> struct Reaction<RD_MODEL_BARKLEY> {
 // J_si = -w (1 + tanh(k_si (u - u_csi))) / (2 tau_si),
 // dv = (1-p)(1-v)/tau_v^-(u) - p v/tau_v^+, dw = (1-p)(1-w)/tau_w^- - p w/tau_w^+.
 template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
-  __device__ __forceinline__ static void rates(const KConst& c, const double* y, double* f) {
+  template <class T>
+  __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const FentonKarmaC& m = c.m.fk;
-    const double u = y[0], v = y[1], w = y[2];
-    const double p = step_h(u - m.u_c, c);
-    const double q = step_h(u - m.u_v, c);
-    const double j_fi = -(((v * p) * (1.0 - u)) * (u - m.u_c)) * m.inv_tau_d;
-    const double j_so = (u * (1.0 - p)) * m.inv_tau_0 + p * m.inv_tau_r;
-    const double j_si = -(w * (1.0 + tanh(m.k_si * (u - m.u_csi)))) * m.inv_2tau_si;
-    const double tau_vm = q * m.tau_v1m + (1.0 - q) * m.tau_v2m;
+    const T u = y[0], v = y[1], w = y[2];
+    const T p = step_h(u - m.u_c, c);
+    const T q = step_h(u - m.u_v, c);
+    const T j_fi = -(((v * p) * (1.0 - u)) * (u - m.u_c)) * m.inv_tau_d;
+    const T j_so = (u * (1.0 - p)) * m.inv_tau_0 + p * m.inv_tau_r;
+    const T j_si = -(w * (2.0 * half_one_plus_tanh(m.k_si * (u - m.u_csi)))) * m.inv_2tau_si;
+    const T tau_vm = q * m.tau_v1m + (1.0 - q) * m.tau_v2m;
     f[0] = -((j_fi + j_so) + j_si);
     f[1] = ((1.0 - p) * (1.0 - v)) / tau_vm - (p * v) * m.inv_tau_vp;
     f[2] = ((1.0 - p) * (1.0 - w)) * m.inv_tau_wm - (p * w) * m.inv_tau_wp;
@@ -127,35 +182,56 @@ template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
 // Bueno-Orovio four-variable model, Eq. (5) with the currents and the
 // alpha/beta gate form; tau(u), v_inf, w_inf as in Bueno-Orovio et al. (2008).
 template <> struct Reaction<RD_MODEL_BOCF> {
-  __device__ __forceinline__ static void rates(const KConst& c, const double* y, double* f) {
+  template <class T>
+  __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const BocfC& m = c.m.bo;
-    const double u = y[0], v = y[1], w = y[2], s = y[3];
-    const double h_v = step_h(u - m.th_v, c);
-    const double h_v_neg = step_h(m.th_v - u, c);
-    const double h_w = step_h(u - m.th_w, c);
-    const double h_w_neg = step_h(m.th_w - u, c);
-    const double h_vm = step_h(u - m.th_vm, c);
-    const double h_o = step_h(u - m.th_o, c);
-    const double tau_vm = (1.0 - h_vm) * m.tau_v1m + h_vm * m.tau_v2m;
-    const double tau_wm = m.tau_w1m + m.dtau_wm * ((1.0 + tanh(m.k_wm * (u - m.u_wm))) * 0.5);
-    const double tau_so = m.tau_so1 + m.dtau_so * ((1.0 + tanh(m.k_so * (u - m.u_so))) * 0.5);
-    const double tau_s = (1.0 - h_w) * m.tau_s1 + h_w * m.tau_s2;
-    const double tau_o = (1.0 - h_o) * m.tau_o1 + h_o * m.tau_o2;
-    const double v_inf = step_h(m.th_vm - u, c);
-    const double w_inf = (1.0 - h_o) * (1.0 - u * m.inv_tau_winf) + h_o * m.w_infstar;
-    const double j_fi = -(((v * h_v) * (u - m.th_v)) * (m.u_u - u)) * m.inv_tau_fi;
-    const double j_so = ((u - m.u_o) * h_w_neg) / tau_o + h_w / tau_so;
-    const double j_si = -((h_w * w) * s) * m.inv_tau_si;
+    const T u = y[0], v = y[1], w = y[2], s = y[3];
+    const T h_v = step_h(u - m.th_v, c);
+    const T h_v_neg = step_h(m.th_v - u, c);
+    const T h_w = step_h(u - m.th_w, c);
+    const T h_w_neg = step_h(m.th_w - u, c);
+    const T h_vm = step_h(u - m.th_vm, c);
+    const T h_o = step_h(u - m.th_o, c);
+    const T tau_vm = (1.0 - h_vm) * m.tau_v1m + h_vm * m.tau_v2m;
+    const T tau_wm = m.tau_w1m + m.dtau_wm * half_one_plus_tanh(m.k_wm * (u - m.u_wm));
+    const T tau_so = m.tau_so1 + m.dtau_so * half_one_plus_tanh(m.k_so * (u - m.u_so));
+    const T tau_s = (1.0 - h_w) * m.tau_s1 + h_w * m.tau_s2;
+    const T tau_o = (1.0 - h_o) * m.tau_o1 + h_o * m.tau_o2;
+    const T v_inf = step_h(m.th_vm - u, c);
+    const T w_inf = (1.0 - h_o) * (1.0 - u * m.inv_tau_winf) + h_o * m.w_infstar;
+    const T j_fi = -(((v * h_v) * (u - m.th_v)) * (m.u_u - u)) * m.inv_tau_fi;
+    const T j_so = ((u - m.u_o) * h_w_neg) / tau_o + h_w / tau_so;
+    const T j_si = -((h_w * w) * s) * m.inv_tau_si;
     f[0] = -((j_fi + j_so) + j_si);
-    const double alpha_v = -(h_v * m.inv_tau_vp) - h_v_neg / tau_vm;
-    const double beta_v = (h_v_neg * v_inf) / tau_vm;
+    const T alpha_v = -(h_v * m.inv_tau_vp) - h_v_neg / tau_vm;
+    const T beta_v = (h_v_neg * v_inf) / tau_vm;
     f[1] = alpha_v * v + beta_v;
-    const double alpha_w = -(h_w * m.inv_tau_wp) - h_w_neg / tau_wm;
-    const double beta_w = (h_w_neg * w_inf) / tau_wm;
+    const T alpha_w = -(h_w * m.inv_tau_wp) - h_w_neg / tau_wm;
+    const T beta_w = (h_w_neg * w_inf) / tau_wm;
     f[2] = alpha_w * w + beta_w;
-    f[3] = ((1.0 + tanh(m.k_s * (u - m.u_s))) * 0.5 - s) / tau_s;
+    f[3] = (half_one_plus_tanh(m.k_s * (u - m.u_s)) - s) / tau_s;
   }
 };
+
+// N(y) (TAN = false) or N(y) and J_N(y) dy (TAN = true) for a packed row
+// y[0..NV) = state, y[NV..2NV) = tangent; results packed the same way.
+template <int MODEL, bool TAN>
+__device__ __forceinline__ void eval_rates(const KConst& c, const double* y, double* k) {
+  constexpr int NV = ModelTraits<MODEL>::NV;
+  if constexpr (!TAN) {
+    Reaction<MODEL>::template rates<double>(c, y, k);
+  } else {
+    Dual yd[NV], kd[NV];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) yd[f] = Dual(y[f], y[NV + f]);
+    Reaction<MODEL>::template rates<Dual>(c, yd, kd);
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+      k[f] = kd[f].v;
+      k[NV + f] = kd[f].d;
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Cross-lane access.  Lane l holds column x0 + l; the previous/next lane holds

@@ -1,6 +1,8 @@
 // rd_host.h -- host-side helpers shared by the C ABI implementation files.
 #pragma once
 
+#include <functional>
+
 #include "rd_device.h"
 
 namespace rd {
@@ -13,7 +15,14 @@ int n_stages(int scheme);
 int validate(const rd_problem* p);
 int validate_fields(const rd_problem* p, double* const* f, const char* what);
 void derive_constants(const rd_problem* p, KConst& c);
-void set_geometry(KConst& c, int ns, int tile_rows);
+void set_geometry(KConst& c, int ns, int ty);
+
+// Autotuned rows per wave band (rd_tune.cpp).  `trial(ty)` enqueues one
+// launch with that band height that writes only workspace.
+enum TuneKind { kTuneForward = 0, kTuneTangent = 1, kTuneAdjoint = 2, kTuneBatched = 3 };
+int heuristic_rows(int nx, int ny, int ns);
+int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns,
+               hipStream_t s, const std::function<hipError_t(int)>& trial);
 size_t align_up(size_t x, size_t a);
 size_t field_bytes(const rd_problem* p);
 int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hipStream_t s);

@@ -1,0 +1,277 @@
+// rd_sweep.h -- fused explicit step: every stage of one Euler / Heun / RK4 step
+// (stencil, reaction and Euler-like update, Sect. 4) in a single kernel, for
+// the state alone or for the state and a tangent in lockstep.
+//
+// Work decomposition.  A wavefront owns a strip of 64 consecutive columns and
+// a band of `ty` rows.  Its lanes hold one column each; a step of NS stages
+// needs NS halo columns on either side, so a strip produces TX = 64 - 2 NS
+// output columns.  The wave sweeps down its band one row per iteration: at
+// iteration r it loads row r of the state and runs stage s on row r - s, so
+// the three rows each stage's stencil needs are already in registers (rows
+// r-s+1 .. r-s-1 of the previous stage's output) and the per-row state (z_n,
+// the stage sum, the gate values of the stage input) lives in small register
+// rings.  Each cell of the state is read once and written once per step;
+// the only redundant work is the NS halo columns and the NS-row ramp at the
+// ends of each band.  x-neighbours come from adjacent lanes (shuffles), so
+// no LDS and no barriers are used.
+//
+// Tangent mode (TAN).  Rows carry 2 NV values: the state and its tangent.
+// The stencil is applied to u and to du (it is linear), the reaction is
+// evaluated on dual numbers (value and derivative along the tangent), and the
+// stage combinations, being linear, act on both halves alike.  The state half
+// is bit-identical to the plain step.
+#pragma once
+
+#include "rd_device.h"
+
+namespace rd {
+
+constexpr int kMaxPacked = 2 * kMaxFields;
+
+struct SweepArgs {
+  const double* in[kMaxPacked];  // state fields, then tangent fields
+  double* out[kMaxPacked];
+  KConst c;
+};
+
+template <int NS> struct Scheme;
+// Euler: z' = z + dt k1.
+template <> struct Scheme<1> {
+  __device__ static double next_coef(const KConst&, int) { return 0.0; }
+};
+// Heun: Y2 = z + dt k1, z' = z + (dt/2)(k1 + k2).
+template <> struct Scheme<2> {
+  __device__ static double next_coef(const KConst& c, int) { return c.dt; }
+};
+// RK4: Y2 = z + (dt/2) k1, Y3 = z + (dt/2) k2, Y4 = z + dt k3,
+// z' = z + (dt/6)(((k1 + 2 k2) + 2 k3) + k4).
+template <> struct Scheme<4> {
+  __device__ static double next_coef(const KConst& c, int s) { return s < 3 ? c.h2 : c.dt; }
+};
+
+// Waves per SIMD each kernel's register budget is sized for (the largest
+// count that still needs no scratch spills).
+template <int MODEL, int STENCIL, int NS, bool TAN> struct SweepOccupancy {
+  static constexpr bool heavy = MODEL == RD_MODEL_BOCF || STENCIL == RD_LAP9_ANISO;
+  static constexpr int value = TAN ? (NS == 4 ? 1 : 2) : (NS == 4 && heavy ? 2 : 3);
+};
+
+template <int MODEL, int STENCIL, int NS, bool TAN>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, TAN>::value)))
+void sweep_kernel(SweepArgs a) {
+  constexpr int NV = ModelTraits<MODEL>::NV;
+  constexpr int NF = TAN ? 2 * NV : NV;  // values per cell carried
+  constexpr int ND = TAN ? 2 : 1;        // diffusive components: u (and du)
+  constexpr int TX = kWave - 2 * NS;
+  constexpr int ZR = (NS + 1 > 3) ? NS + 1 : 3;
+  const KConst& c = a.c;
+  auto comp = [](int d) { return d == 0 ? 0 : NV; };  // index of diffusive component d
+  auto diffusive = [](int f) { return f == 0 || (TAN && f == NV); };
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (wid >= c.nsx * c.nby) return;  // whole waves only: no barrier follows
+  const int sx = wid % c.nsx;
+  const int by = wid / c.nsx;
+  const int gx = sx * TX - NS + lane;
+  const int cx = min(max(gx, 0), c.nx - 1);
+  const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;
+  const Column col = make_column(gx, c, STENCIL == RD_LAP9_ANISO);
+
+  const int yA = by * c.ty;
+  const int yB = min(yA + c.ty, c.ny);
+  const int r_first = max(yA - NS, 0);
+  const int r_last = yB - 1 + NS;
+  const int load_end = min(yB + NS, c.ny);
+  const size_t nx = (size_t)c.nx;
+
+  double zr[ZR][NF];          // zr[a] = z_n at row r - a
+  double acc[NS][NF];         // acc[s-1] = running stage sum of row r - s
+  double yu[NS + 1][3][ND];   // stage-s input u (du) at rows r-s+1, r-s, r-s-1
+  double yg[NS + 1][NF];      // stage-s input, other components, row r - s
+  double ygn[NS + 1][NF];     // ... produced this iteration for row r-s+1
+#pragma unroll
+  for (int k = 0; k < ZR; ++k)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) zr[k][f] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NS; ++k)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[k][f] = 0.0;
+#pragma unroll
+  for (int s = 0; s <= NS; ++s) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) yu[s][0][d] = yu[s][1][d] = yu[s][2][d] = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) yg[s][f] = ygn[s][f] = 0.0;
+  }
+
+  // Rows are prefetched one iteration ahead so that a whole iteration of
+  // arithmetic covers the load latency.
+  double pre[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) pre[f] = 0.0;
+  if (r_first < load_end) {
+    const size_t o = (size_t)r_first * nx + cx;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) pre[f] = a.in[f][o];
+  }
+
+  for (int r = r_first; r <= r_last; ++r) {
+    // Advance the register rings by one row.
+#pragma unroll
+    for (int k = ZR - 1; k > 0; --k)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) zr[k][f] = zr[k - 1][f];
+#pragma unroll
+    for (int k = NS - 1; k > 0; --k)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) acc[k][f] = acc[k - 1][f];
+#pragma unroll
+    for (int s = 2; s <= NS; ++s) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        yu[s][2][d] = yu[s][1][d];
+        yu[s][1][d] = yu[s][0][d];
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        if (!diffusive(f)) yg[s][f] = ygn[s][f];
+    }
+    if (r < load_end) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) zr[0][f] = pre[f];
+      if (r + 1 < load_end) {
+        const size_t o = (size_t)(r + 1) * nx + cx;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) pre[f] = a.in[f][o];
+      }
+    }
+
+#pragma unroll
+    for (int s = 1; s <= NS; ++s) {
+      const int rho = r - s;
+      const int lo = max(yA - (NS - s), 0);
+      const int hi = min(yB + (NS - s), c.ny);
+      if (rho < lo || rho >= hi) continue;  // wave-uniform
+
+      double y[NF], up[ND], dn[ND];
+      if (s == 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) y[f] = zr[1][f];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          up[d] = zr[2][comp(d)];
+          dn[d] = zr[0][comp(d)];
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          if (!diffusive(f)) y[f] = yg[s][f];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          y[comp(d)] = yu[s][1][d];
+          up[d] = yu[s][2][d];
+          dn[d] = yu[s][0][d];
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        if (rho == 0) up[d] = y[comp(d)];
+        if (rho == c.ny - 1) dn[d] = y[comp(d)];
+      }
+
+      double lap[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) lap[d] = diffusion<STENCIL>(up[d], y[comp(d)], dn[d], col, rho, c);
+      double k[NF];
+      eval_rates<MODEL, TAN>(c, y, k);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) k[comp(d)] = lap[d] + k[comp(d)];
+
+      if (NS == 1) {
+        if (out_col && rho >= yA && rho < yB) {
+          const size_t o = (size_t)rho * nx + gx;
+#pragma unroll
+          for (int f = 0; f < NF; ++f) a.out[f][o] = zr[1][f] + c.dt * k[f];
+        }
+        continue;
+      }
+      // stage sum: k1, then + 2 k_s (RK4 middle stages) or + k_s
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        if (s == 1) acc[0][f] = k[f];
+        else if (NS == 4 && s < 4) acc[s - 1][f] = acc[s - 1][f] + 2.0 * k[f];
+        else acc[s - 1][f] = acc[s - 1][f] + k[f];
+      }
+      if (s < NS) {
+        const double cs = Scheme<NS>::next_coef(c, s);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          if (!diffusive(f)) ygn[s + 1][f] = zr[s][f] + cs * k[f];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) yu[s + 1][0][d] = zr[s][comp(d)] + cs * k[comp(d)];
+      } else if (out_col && rho >= yA && rho < yB) {
+        const double bw = NS == 4 ? c.h6 : c.h2;
+        const size_t o = (size_t)rho * nx + gx;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) a.out[f][o] = zr[s][f] + bw * acc[s - 1][f];
+      }
+    }
+  }
+}
+
+template <int MODEL, int STENCIL, int NS, bool TAN>
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
+  const int waves = a.c.nsx * a.c.nby;
+  const int blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, TAN>), dim3(blocks), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+// Dispatch over stencil and scheme for one model and mode.
+template <int MODEL, bool TAN>
+hipError_t launch_sweep_model(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
+  switch (stencil) {
+    case RD_LAP5:
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP5, 1, TAN>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP5, 2, TAN>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP5, 4, TAN>(a, s);
+      break;
+    case RD_LAP9:
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9, 1, TAN>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9, 2, TAN>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9, 4, TAN>(a, s);
+      break;
+    case RD_LAP9_ANISO:
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9_ANISO, 1, TAN>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9_ANISO, 2, TAN>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9_ANISO, 4, TAN>(a, s);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+// Columns each wave produces for a scheme of `ns` stages.
+inline int strip_width(int ns) { return kWave - 2 * ns; }
+
+// One fused step of the state (fwd) or of state and tangent (tan), defined
+// per model in rd_sweep_{fwd,tan}_<model>.hip.
+#define RD_DECLARE_SWEEP(kind, model) \
+  hipError_t launch_sweep_##kind##_##model(int stencil, int scheme, const SweepArgs& a, hipStream_t s);
+RD_DECLARE_SWEEP(fwd, diffusion)
+RD_DECLARE_SWEEP(fwd, barkley)
+RD_DECLARE_SWEEP(fwd, fk)
+RD_DECLARE_SWEEP(fwd, bocf)
+RD_DECLARE_SWEEP(tan, diffusion)
+RD_DECLARE_SWEEP(tan, barkley)
+RD_DECLARE_SWEEP(tan, fk)
+RD_DECLARE_SWEEP(tan, bocf)
+#undef RD_DECLARE_SWEEP
+
+// Dispatch over models.
+hipError_t launch_step_kernel(bool tangent, int model, int stencil, int scheme, const SweepArgs& a,
+                              hipStream_t s);
+
+}  // namespace rd

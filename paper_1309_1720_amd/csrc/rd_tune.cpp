@@ -1,0 +1,108 @@
+// rd_tune.cpp -- band-height autotuner.
+//
+// The rows per wavefront band trade parallelism (more, shorter bands keep more
+// waves in flight) against redundant work (each band end recomputes a ramp of
+// NS rows per stage).  The best value depends on grid shape, model, stencil
+// and scheme, so the first call for each such key times a set of candidates
+// with HIP events on the caller's stream -- trial launches read the caller's
+// state and write only workspace -- and caches the fastest.  Results do not
+// depend on the choice (every band height computes identical bits).
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "rd_host.h"
+
+namespace rd {
+
+namespace {
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int, int, int>, int> g_cache;
+bool g_enabled = true;
+int g_override = -1;
+}  // namespace
+
+void set_tile_rows_override(int rows) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_override = rows;
+}
+
+void set_autotune(bool on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_enabled = on;
+}
+
+int heuristic_rows(int nx, int ny, int ns) {
+  const int tx = 64 - 2 * ns;
+  const int nsx = (nx + tx - 1) / tx;
+  const int target_waves = 2048;
+  const int nby = (target_waves + nsx - 1) / nsx;
+  int ty = (ny + nby - 1) / nby;
+  if (ty < 2 * ns) ty = 2 * ns;
+  return ty < ny ? ty : ny;
+}
+
+int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns,
+               hipStream_t s, const std::function<hipError_t(int)>& trial) {
+  const auto key = std::make_tuple(kind, model, stencil, scheme, nx, ny);
+  const int fallback = heuristic_rows(nx, ny, ns);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_override > 0) return g_override < ny ? g_override : ny;
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) return it->second;
+    if (!g_enabled) return fallback;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return fallback;  // no timing inside a graph capture
+
+  std::vector<int> cands;
+  for (int ty : {2, 3, 4, 6, 8, 10, 12, 16, 24, 32, 48, 64})
+    if (ty <= ny && ty >= ns) cands.push_back(ty);
+  if (cands.empty()) cands.push_back(ny);
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = fallback;
+  bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  if (ok) ok = trial(fallback) == hipSuccess;  // warm-up
+  float best_ms = 1e30f;
+  for (size_t i = 0; ok && i < cands.size(); ++i) {
+    const int reps = 3;
+    ok = hipEventRecord(e0, s) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r) ok = trial(cands[i]) == hipSuccess;
+    ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    if (ok && ms < best_ms) {
+      best_ms = ms;
+      best = cands[i];
+    }
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (!ok) {
+    (void)hipGetLastError();
+    return fallback;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[key] = best;
+  return best;
+}
+
+}  // namespace rd
+
+extern "C" {
+
+int rd_set_tile_rows(int32_t rows) {
+  rd::set_tile_rows_override(rows);
+  return RD_OK;
+}
+
+int rd_set_autotune(int32_t enable) {
+  rd::set_autotune(enable != 0);
+  return RD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+"""GPU parity of rd_jvp (tangent-linear map of the finite-time flow) against
+the oracle's complex-step derivative, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1309_1720_amd as rd
+import rd_inputs as ri
+from rdtest import dev, gpu_step, host, problems, rel_linf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+BASE = {"diffusion": "bocf_2048_aniso_rk4", "barkley": "barkley_1024_rk4_adjoint",
+        "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4"}
+CASES = [(m, st, sc) for m in ("barkley", "fk", "bocf", "diffusion")
+         for st in ("lap5", "lap9", "lap9_aniso") for sc in ("euler", "heun", "rk4")]
+
+
+def setup(model, stencil, scheme, nx, ny, steps, seed=3):
+    w = ri.workload(BASE[model], model=model, stencil=stencil, scheme=scheme, nx=nx, ny=ny)
+    po, pr = problems(w, nsteps=steps)
+    z0 = ri.random_fields(model, nx, ny, seed) if model != "barkley" else ri.barkley_ic(nx, ny, seed)
+    v = ri.direction(len(z0), nx, ny, seed + 100)
+    return po, pr, z0, v
+
+
+def gpu_jvp(pr, z0, v):
+    zt, vt = dev(z0), dev(v)
+    rd.jvp(pr, zt, vt)
+    return host(zt), host(vt)
+
+
+@pytest.mark.parametrize("model,stencil,scheme", CASES)
+def test_jvp_matches_oracle(model, stencil, scheme):
+    po, pr, z0, v = setup(model, stencil, scheme, 97, 61, 17)
+    z_ref, jv_ref = oracle.jvp(po, z0, v, 17)
+    z_gpu, jv_gpu = gpu_jvp(pr, z0, v)
+    err = rel_linf(jv_gpu, jv_ref)
+    print(f"{model} {stencil} {scheme}: tangent rel-Linf {err:.3e}")
+    assert err <= TOL
+    # the state half is the plain step, bit for bit
+    z_fwd = gpu_step(pr, z0)
+    assert all(np.array_equal(a, b) for a, b in zip(z_gpu, z_fwd))
+
+
+@pytest.mark.parametrize("model,stencil,n,steps", [("fk", "lap9", 128, 200), ("barkley", "lap5", 130, 300),
+                                                   ("bocf", "lap9_aniso", 96, 150)])
+def test_jvp_long_horizon(model, stencil, n, steps):
+    po, pr, z0, v = setup(model, stencil, "rk4", n, n, steps, seed=11)
+    if model == "fk":
+        z0 = ri.fk_ic(n, n, 4000)
+    _, jv_ref = oracle.jvp(po, z0, v, steps)
+    _, jv_gpu = gpu_jvp(pr, z0, v)
+    err = rel_linf(jv_gpu, jv_ref)
+    print(f"{model} {n}^2 {steps} steps: tangent rel-Linf {err:.3e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("n", [256, 768])
+def test_jvp_agrees_with_central_differences_full_size(n):
+    """Ensemble grid sizes: the exact JVP and GPU central differences agree to
+    the finite-difference truncation/rounding level."""
+    w = ri.workload("fk_1024_rk4", nx=n, ny=n)
+    _, pr = problems(w, nsteps=100)
+    z0 = ri.fk_ic(n, n, 4000)
+    v = ri.direction(3, n, n, 4100)
+    _, jv = gpu_jvp(pr, z0, v)
+    eps = 1e-6
+    zp = gpu_step(pr, [a + eps * b for a, b in zip(z0, v)])
+    zm = gpu_step(pr, [a - eps * b for a, b in zip(z0, v)])
+    fd = [(a - b) / (2 * eps) for a, b in zip(zp, zm)]
+    num = np.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(fd, jv)))
+    den = np.sqrt(sum(float(np.sum(y ** 2)) for y in jv))
+    assert num / den < 1e-6
+
+
+def test_jvp_band_height_invariance_and_linearity():
+    po, pr, z0, v = setup("fk", "lap9", "rk4", 150, 90, 9)
+    outs = []
+    try:
+        for rows in (0, 2, 7, 90):
+            rd.set_tile_rows(rows)
+            outs.append(gpu_jvp(pr, z0, v)[1])
+    finally:
+        rd.set_tile_rows(0)
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
+    _, a = gpu_jvp(pr, z0, v)
+    _, b = gpu_jvp(pr, z0, [2.0 * x for x in v])
+    assert all(np.array_equal(2.0 * x, y) for x, y in zip(a, b))  # scaling by 2 is exact
