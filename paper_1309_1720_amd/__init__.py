@@ -11,3 +11,4 @@ from ._binding import (  # noqa: F401
     step_batched,
     vjp, workspace_bytes,
 )
+from .autograd import RDFlow, flow  # noqa: F401,E402

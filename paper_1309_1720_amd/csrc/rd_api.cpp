@@ -202,20 +202,22 @@ size_t field_bytes(const rd_problem* p) {
   return align_up((size_t)p->nx * (size_t)p->ny * sizeof(double), 256);
 }
 
-hipError_t launch_step_kernel(bool tangent, int model, int stencil, int scheme, const SweepArgs& a,
-                              hipStream_t s) {
+hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const SweepArgs& a,
+                             hipStream_t s) {
+#define RD_MODE_SWITCH(name)                                              \
+  switch (mode) {                                                         \
+    case kModeStep: return launch_sweep_fwd_##name(stencil, scheme, a, s); \
+    case kModeTangent: return launch_sweep_tan_##name(stencil, scheme, a, s); \
+    case kModeStages: return launch_sweep_stg_##name(stencil, scheme, a, s); \
+  }                                                                       \
+  break;
   switch (model) {
-    case RD_MODEL_DIFFUSION:
-      return tangent ? launch_sweep_tan_diffusion(stencil, scheme, a, s)
-                     : launch_sweep_fwd_diffusion(stencil, scheme, a, s);
-    case RD_MODEL_BARKLEY:
-      return tangent ? launch_sweep_tan_barkley(stencil, scheme, a, s)
-                     : launch_sweep_fwd_barkley(stencil, scheme, a, s);
-    case RD_MODEL_FENTON_KARMA:
-      return tangent ? launch_sweep_tan_fk(stencil, scheme, a, s) : launch_sweep_fwd_fk(stencil, scheme, a, s);
-    case RD_MODEL_BOCF:
-      return tangent ? launch_sweep_tan_bocf(stencil, scheme, a, s) : launch_sweep_fwd_bocf(stencil, scheme, a, s);
+    case RD_MODEL_DIFFUSION: RD_MODE_SWITCH(diffusion)
+    case RD_MODEL_BARKLEY: RD_MODE_SWITCH(barkley)
+    case RD_MODEL_FENTON_KARMA: RD_MODE_SWITCH(fk)
+    case RD_MODEL_BOCF: RD_MODE_SWITCH(bocf)
   }
+#undef RD_MODE_SWITCH
   return hipErrorInvalidValue;
 }
 
@@ -264,7 +266,7 @@ int run_steps(const rd_problem* p, const KConst& c, bool tangent, double* const*
       args.in[f] = cur[f];
       args.out[f] = oth[f];
     }
-    hipError_t e = launch_step_kernel(tangent, p->model, p->stencil, p->scheme, args, s);
+    hipError_t e = launch_sweep_mode(tangent ? kModeTangent : kModeStep, p->model, p->stencil, p->scheme, args, s);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     std::swap(cur, oth);
   }
@@ -286,7 +288,7 @@ void plan_geometry(const rd_problem* p, KConst& c, bool tangent, double* const* 
       a.in[f] = in[f];
       a.out[f] = out[f];
     }
-    return launch_step_kernel(tangent, p->model, p->stencil, p->scheme, a, s);
+    return launch_sweep_mode(tangent ? kModeTangent : kModeStep, p->model, p->stencil, p->scheme, a, s);
   };
   const int ty = tuned_rows(tangent ? kTuneTangent : kTuneForward, p->model, p->stencil, p->scheme,
                             p->nx, p->ny, ns, s, trial);

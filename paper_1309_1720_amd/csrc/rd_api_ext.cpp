@@ -2,19 +2,10 @@
 #include "rd_host.h"
 
 namespace rd {
-int workspace_vjp(const rd_problem* p, size_t* out) {
-  *out = 0;
-  return fail(RD_EUNSUPPORTED, "rd_vjp is not available in this build");
-}
 }  // namespace rd
 
 using namespace rd;
 extern "C" {
-int rd_vjp(const rd_problem* p, const double*, double* const*, void*, size_t, void*) {
-  int rc = validate(p);
-  if (rc) return rc;
-  return fail(RD_EUNSUPPORTED, "rd_vjp is not available in this build");
-}
 int rd_step_batched_workspace_bytes(const rd_problem*, int32_t, int32_t, size_t*) {
   return fail(RD_EUNSUPPORTED, "rd_step_batched is not available in this build");
 }

@@ -28,9 +28,17 @@ namespace rd {
 
 constexpr int kMaxPacked = 2 * kMaxFields;
 
+// What a sweep launch produces.
+enum SweepMode {
+  kModeStep = 0,     // z_{n+1} from z_n
+  kModeTangent = 1,  // (z_{n+1}, dz_{n+1}) from (z_n, dz_n)
+  kModeStages = 2    // the stage inputs Y_2 .. Y_NS of the step from z_n
+};
+
 struct SweepArgs {
   const double* in[kMaxPacked];  // state fields, then tangent fields
-  double* out[kMaxPacked];
+  double* out[kMaxPacked];       // step / tangent modes
+  double* ys[3][kMaxFields];     // stages mode: Y_{s+1} fields, s = 1 .. NS-1
   KConst c;
 };
 
@@ -51,15 +59,18 @@ template <> struct Scheme<4> {
 
 // Waves per SIMD each kernel's register budget is sized for (the largest
 // count that still needs no scratch spills).
-template <int MODEL, int STENCIL, int NS, bool TAN> struct SweepOccupancy {
+template <int MODEL, int STENCIL, int NS, int MODE> struct SweepOccupancy {
   static constexpr bool heavy = MODEL == RD_MODEL_BOCF || STENCIL == RD_LAP9_ANISO;
-  static constexpr int value = TAN ? (NS == 4 ? 1 : 2) : (NS == 4 && heavy ? 2 : 3);
+  static constexpr int value =
+      MODE == kModeTangent ? (NS == 4 ? 1 : 2) : (NS == 4 && heavy ? 2 : 3);
 };
 
-template <int MODEL, int STENCIL, int NS, bool TAN>
+template <int MODEL, int STENCIL, int NS, int MODE>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, TAN>::value)))
+__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
 void sweep_kernel(SweepArgs a) {
+  constexpr bool TAN = MODE == kModeTangent;
+  constexpr bool STAGES = MODE == kModeStages;
   constexpr int NV = ModelTraits<MODEL>::NV;
   constexpr int NF = TAN ? 2 * NV : NV;  // values per cell carried
   constexpr int ND = TAN ? 2 : 1;        // diffusive components: u (and du)
@@ -151,6 +162,7 @@ void sweep_kernel(SweepArgs a) {
 
 #pragma unroll
     for (int s = 1; s <= NS; ++s) {
+      if (STAGES && s == NS) continue;  // k_NS is not a stage input
       const int rho = r - s;
       const int lo = max(yA - (NS - s), 0);
       const int hi = min(yB + (NS - s), c.ny);
@@ -212,7 +224,13 @@ void sweep_kernel(SweepArgs a) {
           if (!diffusive(f)) ygn[s + 1][f] = zr[s][f] + cs * k[f];
 #pragma unroll
         for (int d = 0; d < ND; ++d) yu[s + 1][0][d] = zr[s][comp(d)] + cs * k[comp(d)];
-      } else if (out_col && rho >= yA && rho < yB) {
+        if (STAGES && out_col && rho >= yA && rho < yB) {
+          const size_t o = (size_t)rho * nx + gx;
+          a.ys[s - 1][0][o] = yu[s + 1][0][0];
+#pragma unroll
+          for (int f = 1; f < NV; ++f) a.ys[s - 1][f][o] = ygn[s + 1][f];
+        }
+      } else if (!STAGES && out_col && rho >= yA && rho < yB) {
         const double bw = NS == 4 ? c.h6 : c.h2;
         const size_t o = (size_t)rho * nx + gx;
 #pragma unroll
@@ -222,32 +240,33 @@ void sweep_kernel(SweepArgs a) {
   }
 }
 
-template <int MODEL, int STENCIL, int NS, bool TAN>
+template <int MODEL, int STENCIL, int NS, int MODE>
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
+  if (MODE == kModeStages && NS == 1) return hipSuccess;  // Euler has no inner stage
   const int waves = a.c.nsx * a.c.nby;
   const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, TAN>), dim3(blocks), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE>), dim3(blocks), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 
 // Dispatch over stencil and scheme for one model and mode.
-template <int MODEL, bool TAN>
+template <int MODEL, int MODE>
 hipError_t launch_sweep_model(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
   switch (stencil) {
     case RD_LAP5:
-      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP5, 1, TAN>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP5, 2, TAN>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP5, 4, TAN>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP5, 1, MODE>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP5, 2, MODE>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP5, 4, MODE>(a, s);
       break;
     case RD_LAP9:
-      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9, 1, TAN>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9, 2, TAN>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9, 4, TAN>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9, 1, MODE>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9, 2, MODE>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9, 4, MODE>(a, s);
       break;
     case RD_LAP9_ANISO:
-      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9_ANISO, 1, TAN>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9_ANISO, 2, TAN>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9_ANISO, 4, TAN>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9_ANISO, 1, MODE>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9_ANISO, 2, MODE>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9_ANISO, 4, MODE>(a, s);
       break;
   }
   return hipErrorInvalidValue;
@@ -256,8 +275,8 @@ hipError_t launch_sweep_model(int stencil, int scheme, const SweepArgs& a, hipSt
 // Columns each wave produces for a scheme of `ns` stages.
 inline int strip_width(int ns) { return kWave - 2 * ns; }
 
-// One fused step of the state (fwd) or of state and tangent (tan), defined
-// per model in rd_sweep_{fwd,tan}_<model>.hip.
+// One fused step of the state (fwd), of state and tangent (tan), or the
+// stage inputs of a step (stg), defined per model in rd_sweep_<kind>_<model>.hip.
 #define RD_DECLARE_SWEEP(kind, model) \
   hipError_t launch_sweep_##kind##_##model(int stencil, int scheme, const SweepArgs& a, hipStream_t s);
 RD_DECLARE_SWEEP(fwd, diffusion)
@@ -268,10 +287,14 @@ RD_DECLARE_SWEEP(tan, diffusion)
 RD_DECLARE_SWEEP(tan, barkley)
 RD_DECLARE_SWEEP(tan, fk)
 RD_DECLARE_SWEEP(tan, bocf)
+RD_DECLARE_SWEEP(stg, diffusion)
+RD_DECLARE_SWEEP(stg, barkley)
+RD_DECLARE_SWEEP(stg, fk)
+RD_DECLARE_SWEEP(stg, bocf)
 #undef RD_DECLARE_SWEEP
 
 // Dispatch over models.
-hipError_t launch_step_kernel(bool tangent, int model, int stencil, int scheme, const SweepArgs& a,
-                              hipStream_t s);
+hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const SweepArgs& a,
+                             hipStream_t s);
 
 }  // namespace rd

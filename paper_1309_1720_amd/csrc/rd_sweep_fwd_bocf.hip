@@ -3,6 +3,6 @@
 
 namespace rd {
 hipError_t launch_sweep_fwd_bocf(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
-  return launch_sweep_model<RD_MODEL_BOCF, false>(stencil, scheme, a, stream);
+  return launch_sweep_model<RD_MODEL_BOCF, kModeStep>(stencil, scheme, a, stream);
 }
 }  // namespace rd

@@ -3,6 +3,6 @@
 
 namespace rd {
 hipError_t launch_sweep_fwd_diffusion(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
-  return launch_sweep_model<RD_MODEL_DIFFUSION, false>(stencil, scheme, a, stream);
+  return launch_sweep_model<RD_MODEL_DIFFUSION, kModeStep>(stencil, scheme, a, stream);
 }
 }  // namespace rd

@@ -3,6 +3,6 @@
 
 namespace rd {
 hipError_t launch_sweep_fwd_fk(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
-  return launch_sweep_model<RD_MODEL_FENTON_KARMA, false>(stencil, scheme, a, stream);
+  return launch_sweep_model<RD_MODEL_FENTON_KARMA, kModeStep>(stencil, scheme, a, stream);
 }
 }  // namespace rd

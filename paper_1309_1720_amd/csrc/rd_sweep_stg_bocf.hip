@@ -1,0 +1,8 @@
+// Fused-step kernels of the bocf model producing the stage inputs of a step, all stencils and schemes.
+#include "rd_sweep.h"
+
+namespace rd {
+hipError_t launch_sweep_stg_bocf(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
+  return launch_sweep_model<RD_MODEL_BOCF, kModeStages>(stencil, scheme, a, stream);
+}
+}  // namespace rd

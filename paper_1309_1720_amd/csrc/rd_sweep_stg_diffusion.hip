@@ -1,0 +1,8 @@
+// Fused-step kernels of the diffusion model producing the stage inputs of a step, all stencils and schemes.
+#include "rd_sweep.h"
+
+namespace rd {
+hipError_t launch_sweep_stg_diffusion(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
+  return launch_sweep_model<RD_MODEL_DIFFUSION, kModeStages>(stencil, scheme, a, stream);
+}
+}  // namespace rd

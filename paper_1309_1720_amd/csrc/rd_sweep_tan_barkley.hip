@@ -1,8 +1,8 @@
-// Fused-step kernels of the barkley model advancing the state and tangent, all stencils and schemes.
+// Fused-step kernels of the barkley model advancing the state and a tangent, all stencils and schemes.
 #include "rd_sweep.h"
 
 namespace rd {
 hipError_t launch_sweep_tan_barkley(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
-  return launch_sweep_model<RD_MODEL_BARKLEY, true>(stencil, scheme, a, stream);
+  return launch_sweep_model<RD_MODEL_BARKLEY, kModeTangent>(stencil, scheme, a, stream);
 }
 }  // namespace rd

@@ -1,0 +1,143 @@
+"""GPU parity of rd_vjp (adjoint of the finite-time flow) against the oracle,
+the dot-product test against rd_jvp, and the autograd wrapper."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1309_1720_amd as rd
+import rd_inputs as ri
+from rdtest import dev, gpu_step, host, problems, rel_linf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+BASE = {"diffusion": "barkley_1024_rk4_adjoint", "barkley": "barkley_1024_rk4_adjoint",
+        "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4"}
+CASES = [(m, st, sc) for m in ("barkley", "fk", "bocf", "diffusion")
+         for st in ("lap5", "lap9") for sc in ("euler", "heun", "rk4")]
+
+
+def setup(model, stencil, scheme, nx, ny, steps, every, seed=3):
+    w = ri.workload(BASE[model], model=model, stencil=stencil, scheme=scheme, nx=nx, ny=ny,
+                    checkpoint_every=every)
+    po, pr = problems(w, nsteps=steps)
+    if model == "barkley":
+        z0 = ri.barkley_ic(nx, ny, seed)
+    elif model == "fk":
+        z0 = ri.fk_ic(nx, ny, seed)
+    else:
+        z0 = ri.random_fields(model, nx, ny, seed)
+    return po, pr, z0
+
+
+def gpu_vjp(pr, z0, lam):
+    zt = dev(z0)
+    ck = torch.zeros(max(rd.checkpoint_count(pr), 1) * pr.nfields * pr.nx * pr.ny,
+                     dtype=torch.float64, device="cuda")
+    rd.step(pr, zt, ck)
+    lt = dev(lam)
+    rd.vjp(pr, ck, lt)
+    return host(lt)
+
+
+@pytest.mark.parametrize("model,stencil,scheme", CASES)
+def test_vjp_matches_oracle(model, stencil, scheme):
+    """97 x 61, 13 steps, checkpoints every 5 (ragged last segment)."""
+    po, pr, z0 = setup(model, stencil, scheme, 97, 61, 13, 5)
+    lam = ri.direction(len(z0), 97, 61, 77)
+    ref = oracle.vjp(po, z0, lam, 13, checkpoint_every=5)
+    got = gpu_vjp(pr, z0, lam)
+    err = rel_linf(got, ref)
+    print(f"{model} {stencil} {scheme}: adjoint rel-Linf {err:.3e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("steps,every", [(1, 1), (2, 64), (7, 3), (64, 64), (65, 64)])
+def test_vjp_segmentation(steps, every):
+    po, pr, z0 = setup("barkley", "lap5", "rk4", 70, 50, steps, every)
+    lam = ri.direction(2, 70, 50, 5)
+    ref = oracle.vjp(po, z0, lam, steps, checkpoint_every=7)
+    assert rel_linf(gpu_vjp(pr, z0, lam), ref) <= TOL
+
+
+def test_adjoint_loss_gradient_barkley_long():
+    """Gradient of L = sum u(T)^2 dx^2 over 1000 RK4 steps (the adjoint
+    workload on a 160 x 128 grid), checkpoints every 64."""
+    po, pr, z0 = setup("barkley", "lap5", "rk4", 160, 128, 1000, 64, seed=5)
+    zT = oracle.step(po, z0, 1000)
+    lam = [2.0 * po.dx ** 2 * zT[0], np.zeros_like(zT[1])]
+    ref = oracle.vjp(po, z0, lam, 1000, checkpoint_every=64)
+    got = gpu_vjp(pr, z0, lam)
+    err = rel_linf(got, ref)
+    print(f"barkley 160x128 1000 steps: adjoint rel-Linf {err:.3e}")
+    assert err <= TOL
+
+
+def dot(a, b):
+    return sum(float(np.sum(x * y)) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("model,stencil,n,steps", [("barkley", "lap5", 256, 400), ("fk", "lap9", 192, 200),
+                                                   ("bocf", "lap9", 96, 60)])
+def test_dot_product_jvp_vjp(model, stencil, n, steps):
+    po, pr, z0 = setup(model, stencil, "rk4", n, n, steps, 64, seed=5)
+    nv = len(z0)
+    v = ri.direction(nv, n, n, 5100)
+    w = ri.direction(nv, n, n, 5101)
+    zt, vt = dev(z0), dev(v)
+    rd.jvp(pr, zt, vt)
+    jv = host(vt)
+    jtw = gpu_vjp(pr, z0, w)
+    a, b = dot(jv, w), dot(v, jtw)
+    rel = abs(a - b) / max(abs(a), abs(b))
+    print(f"{model} {n}^2 {steps}: <Jv,w>={a:.15e} <v,J^T w>={b:.15e} rel {rel:.2e}")
+    assert rel <= 1e-12
+
+
+@pytest.mark.slow
+def test_adjoint_workload_full_size_dot_and_fd():
+    """Barkley 1024^2, RK4, 4000 steps, checkpoints every 64: dot-product test
+    against the JVP and central differences in 4 seeded directions."""
+    w = ri.workload("barkley_1024_rk4_adjoint")
+    _, pr = problems(w)
+    z0 = ri.initial_condition(w)
+    zT = gpu_step(pr, z0)
+    lam = [2.0 * w["dx"] ** 2 * zT[0], np.zeros_like(zT[1])]
+    g = gpu_vjp(pr, z0, lam)
+    loss = lambda z: float(np.sum(z[0] ** 2) * w["dx"] ** 2)
+    for k in range(4):
+        v = ri.direction(2, 1024, 1024, 5000 + k)
+        eps = 1e-6
+        lp = loss(gpu_step(pr, [a + eps * b for a, b in zip(z0, v)]))
+        lm = loss(gpu_step(pr, [a - eps * b for a, b in zip(z0, v)]))
+        fd = (lp - lm) / (2 * eps)
+        ad = dot(g, v)
+        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-12), (k, fd, ad)
+    v = ri.direction(2, 1024, 1024, 5100)
+    zt, vt = dev(z0), dev(v)
+    rd.jvp(pr, zt, vt)
+    a, b = dot(host(vt), lam), dot(v, g)
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+def test_autograd_flow_matches_oracle_gradient():
+    po, pr, z0 = setup("barkley", "lap9", "rk4", 80, 72, 150, 32, seed=9)
+    u0 = torch.from_numpy(z0[0]).cuda().requires_grad_(True)
+    v0 = torch.from_numpy(z0[1]).cuda().requires_grad_(True)
+    uT, vT = rd.flow(pr, u0, v0)
+    loss = (uT * uT).sum() * po.dx ** 2 + (vT * uT).sum()
+    loss.backward()
+    zT = oracle.step(po, z0, 150)
+    lam = [2.0 * po.dx ** 2 * zT[0] + zT[1], zT[0]]
+    ref = oracle.vjp(po, z0, lam, 150, checkpoint_every=32)
+    assert rel_linf([u0.grad.cpu().numpy(), v0.grad.cpu().numpy()], ref) <= TOL
+
+
+def test_vjp_rejects_anisotropic_stencil():
+    po, pr, z0 = setup("bocf", "lap9_aniso", "rk4", 32, 32, 4, 2)
+    ck = torch.zeros(2 * 4 * 32 * 32, dtype=torch.float64, device="cuda")
+    with pytest.raises(rd.RDError, match="RD_EUNSUPPORTED"):
+        rd.vjp(pr, ck, dev(z0))
