@@ -1,0 +1,174 @@
+// rd_api_batch.cpp -- rd_step_batched: validation, workspace layout and the
+// launch sequence (descriptor setup, optional copy, one launch per step).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "rd_batch.h"
+#include "rd_host.h"
+
+namespace rd {
+
+static hipError_t launch_batch_kernel(bool tangent, int model, int stencil, int scheme,
+                                      const BatchArgs& a, hipStream_t s) {
+  switch (model) {
+    case RD_MODEL_DIFFUSION: return launch_batch_diffusion(tangent, stencil, scheme, a, s);
+    case RD_MODEL_BARKLEY: return launch_batch_barkley(tangent, stencil, scheme, a, s);
+    case RD_MODEL_FENTON_KARMA: return launch_batch_fk(tangent, stencil, scheme, a, s);
+    case RD_MODEL_BOCF: return launch_batch_bocf(tangent, stencil, scheme, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Everything except the grid size must agree across the batch.
+static int check_uniform(const rd_problem* probs, int32_t n) {
+  const rd_problem& q = probs[0];
+  for (int32_t i = 1; i < n; ++i) {
+    const rd_problem& p = probs[i];
+    const bool aniso = q.stencil == RD_LAP9_ANISO;
+    if (p.model != q.model || p.scheme != q.scheme || p.stencil != q.stencil || p.bc != q.bc ||
+        p.dx != q.dx || p.dt != q.dt || p.nsteps != q.nsteps || p.D_par != q.D_par ||
+        p.step_k != q.step_k || p.nparams != q.nparams ||
+        (aniso && (p.D_perp != q.D_perp || p.theta0 != q.theta0 || p.theta1 != q.theta1)))
+      return fail(RD_EUNSUPPORTED, "problem %d differs from problem 0 in more than its grid size", i);
+    if (q.nparams > 0 && std::memcmp(p.params, q.params, sizeof(double) * q.nparams) != 0)
+      return fail(RD_EUNSUPPORTED, "problem %d has different model parameters from problem 0", i);
+  }
+  return RD_OK;
+}
+
+static size_t table_bytes(int32_t n) { return align_up(sizeof(BatchInst) * (size_t)n, 256); }
+
+static int batch_workspace(const rd_problem* probs, int32_t n, bool tangent, size_t* out) {
+  if (!probs) return fail(RD_EINVAL, "problems is NULL");
+  if (n < 1 || n > 65536) return fail(RD_EINVAL, "nbatch %d outside [1, 65536]", n);
+  size_t total = table_bytes(n);
+  for (int32_t i = 0; i < n; ++i) {
+    int rc = validate(&probs[i]);
+    if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
+    total += (tangent ? 2 : 1) * (size_t)n_fields(probs[i].model) * field_bytes(&probs[i]);
+  }
+  *out = total;
+  return RD_OK;
+}
+
+}  // namespace rd
+
+using namespace rd;
+
+extern "C" int rd_step_batched_workspace_bytes(const rd_problem* probs, int32_t nbatch,
+                                               int32_t with_tangents, size_t* out) {
+  if (!out) return fail(RD_EINVAL, "out is NULL");
+  return batch_workspace(probs, nbatch, with_tangents != 0, out);
+}
+
+extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* const* fields,
+                               double* const* const* tangents, void* ws, size_t ws_bytes,
+                               void* hip_stream) {
+  const bool tangent = tangents != nullptr;
+  size_t need = 0;
+  int rc = batch_workspace(probs, nbatch, tangent, &need);
+  if (rc) return rc;
+  rc = check_uniform(probs, nbatch);
+  if (rc) return rc;
+  if (!fields) return fail(RD_EINVAL, "fields is NULL");
+  const rd_problem& q = probs[0];
+  const int nv = n_fields(q.model);
+  const int nf = (tangent ? 2 : 1) * nv;
+  for (int32_t i = 0; i < nbatch; ++i) {
+    rc = validate_fields(&probs[i], fields[i], "fields");
+    if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
+    if (tangent) {
+      rc = validate_fields(&probs[i], tangents[i], "tangents");
+      if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
+    }
+  }
+  if (q.nsteps == 0) return RD_OK;
+  if (!ws || ws_bytes < need)
+    return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+  if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
+
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int ns = n_stages(q.scheme);
+  BatchInst* table = (BatchInst*)ws;
+  std::vector<BatchInst> inst(nbatch);
+  char* next = (char*)ws + table_bytes(nbatch);
+  int max_ny = 1;
+  uint32_t shape_hash = 2166136261u;
+  for (int32_t i = 0; i < nbatch; ++i) {
+    BatchInst& I = inst[i];
+    std::memset(&I, 0, sizeof I);
+    I.nx = probs[i].nx;
+    I.ny = probs[i].ny;
+    for (int f = 0; f < nf; ++f) {
+      I.a[f] = f < nv ? fields[i][f] : tangents[i][f - nv];
+      I.b[f] = (double*)next;
+      next += field_bytes(&probs[i]);
+    }
+    max_ny = std::max(max_ny, I.ny);
+    shape_hash = (shape_hash ^ (uint32_t)I.nx) * 16777619u;
+    shape_hash = (shape_hash ^ (uint32_t)I.ny) * 16777619u;
+  }
+
+  BatchArgs args;
+  std::memset(&args, 0, sizeof args);
+  derive_constants(&q, args.c);
+  args.table = table;
+  args.ninst = nbatch;
+  args.nf = nf;
+
+  // Per-instance geometry for `ty` rows per band, and the table upload.
+  auto plan = [&](int ty) -> hipError_t {
+    int waves = 0;
+    for (auto& I : inst) {
+      KConst g;
+      g.nx = I.nx;
+      g.ny = I.ny;
+      set_geometry(g, ns, ty);
+      I.nsx = g.nsx;
+      I.nby = g.nby;
+      I.ty = g.ty;
+      I.wave_begin = waves;
+      waves += g.nsx * g.nby;
+    }
+    args.total_waves = waves;
+    for (int32_t first = 0; first < nbatch; first += kInstPerSetup) {
+      BatchSetupArgs sa;
+      std::memset(&sa, 0, sizeof sa);
+      sa.table = table;
+      sa.first = first;
+      sa.count = std::min(kInstPerSetup, nbatch - first);
+      for (int k = 0; k < sa.count; ++k) sa.inst[k] = inst[first + k];
+      hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(kInstPerSetup), 0, s, sa);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  auto trial = [&](int ty) -> hipError_t {
+    hipError_t e = plan(ty);
+    if (e != hipSuccess) return e;
+    args.parity = 0;  // reads the caller's arrays, writes workspace only
+    return launch_batch_kernel(tangent, q.model, q.stencil, q.scheme, args, s);
+  };
+  const int ty = tuned_rows(kTuneBatched + (tangent ? 8 : 0), q.model, q.stencil, q.scheme,
+                            (int)(shape_hash & 0x7fffffff), max_ny, ns, s, trial);
+  hipError_t e = plan(ty);
+  if (e != hipSuccess) return hip_fail(e, "batch table setup");
+
+  int parity = 0;
+  if (q.nsteps % 2 == 1) {  // an odd number of steps must end in the caller's arrays
+    BatchCopyArgs ca{table, nf};
+    hipLaunchKernelGGL(batch_copy_kernel, dim3(64, nbatch), dim3(256), 0, s, ca);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batch copy launch");
+    parity = 1;
+  }
+  for (int64_t n = 0; n < q.nsteps; ++n) {
+    args.parity = parity;
+    e = launch_batch_kernel(tangent, q.model, q.stencil, q.scheme, args, s);
+    if (e != hipSuccess) return hip_fail(e, "batched step launch");
+    parity ^= 1;
+  }
+  return RD_OK;
+}

@@ -1,0 +1,124 @@
+// rd_batch.h -- one fused step of many independent problems (an ensemble or a
+// set of Krylov directions) on grids of different sizes, in a single launch.
+//
+// Every instance is cut into 64-column strips and row bands exactly as a
+// single-grid launch would cut it; the waves of all instances are numbered
+// consecutively and each wave looks its instance up in a device-side table
+// (binary search over the first wave of each instance, in scalar registers),
+// then runs the same per-wave sweep as rd_step / rd_jvp.  Results are
+// therefore bit-identical to per-instance calls.
+//
+// The table is written by a small setup kernel that receives the instance
+// descriptors as kernel arguments, so no host buffer has to outlive the call
+// and the whole sequence consists of kernel launches only.
+#pragma once
+
+#include "rd_sweep.h"
+
+namespace rd {
+
+struct BatchInst {
+  double* a[kMaxPacked];  // caller's arrays: state fields, then tangent fields
+  double* b[kMaxPacked];  // equally sized workspace arrays (ping-pong partner)
+  int nx, ny, nsx, nby, ty;
+  int wave_begin;         // first global wave of this instance
+};
+
+constexpr int kInstPerSetup = 24;  // descriptors per setup launch (< 4 KiB of arguments)
+
+struct BatchSetupArgs {
+  BatchInst inst[kInstPerSetup];
+  BatchInst* table;
+  int first, count;
+};
+
+struct BatchArgs {
+  const BatchInst* table;
+  int ninst;
+  int total_waves;
+  int parity;   // 0: a -> b, 1: b -> a
+  int nf;       // arrays per instance
+  KConst c;     // shared physics; grid fields are taken from the table
+};
+
+struct BatchCopyArgs {
+  const BatchInst* table;
+  int nf;
+};
+
+__global__ void batch_setup_kernel(BatchSetupArgs a);
+__global__ void batch_copy_kernel(BatchCopyArgs a);
+
+template <int MODEL, int STENCIL, int NS, int MODE>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
+void batch_sweep_kernel(BatchArgs a) {
+  constexpr int NF = (MODE == kModeTangent ? 2 : 1) * ModelTraits<MODEL>::NV;
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+  if (wid >= a.total_waves) return;  // whole waves only: no barrier follows
+  int lo = 0, hi = a.ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.table[mid].wave_begin <= wid) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const BatchInst& I = a.table[lo];
+  KConst c = a.c;
+  c.nx = I.nx;
+  c.ny = I.ny;
+  c.nsx = I.nsx;
+  c.nby = I.nby;
+  c.ty = I.ty;
+  c.n_total = (double)I.nx;
+  const double* in[kMaxPacked];
+  double* out[kMaxPacked];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    in[f] = a.parity ? I.b[f] : I.a[f];
+    out[f] = a.parity ? I.a[f] : I.b[f];
+  }
+  double* const no_stages[3][kMaxFields] = {};
+  sweep_wave<MODEL, STENCIL, NS, MODE>(in, out, no_stages, c, wid - I.wave_begin);
+}
+
+template <int MODEL, int STENCIL, int NS, int MODE>
+hipError_t launch_batch(const BatchArgs& a, hipStream_t stream) {
+  const int blocks = (a.total_waves + 3) / 4;
+  hipLaunchKernelGGL((batch_sweep_kernel<MODEL, STENCIL, NS, MODE>), dim3(blocks), dim3(256), 0,
+                     stream, a);
+  return hipGetLastError();
+}
+
+template <int MODEL, int MODE>
+hipError_t launch_batch_model(int stencil, int scheme, const BatchArgs& a, hipStream_t s) {
+  switch (stencil) {
+    case RD_LAP5:
+      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP5, 1, MODE>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP5, 2, MODE>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP5, 4, MODE>(a, s);
+      break;
+    case RD_LAP9:
+      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9, 1, MODE>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9, 2, MODE>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9, 4, MODE>(a, s);
+      break;
+    case RD_LAP9_ANISO:
+      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9_ANISO, 2, MODE>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9_ANISO, 4, MODE>(a, s);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+#define RD_DECLARE_BATCH(model)                                                           \
+  hipError_t launch_batch_##model(bool tangent, int stencil, int scheme, const BatchArgs& a, \
+                                  hipStream_t s);
+RD_DECLARE_BATCH(diffusion)
+RD_DECLARE_BATCH(barkley)
+RD_DECLARE_BATCH(fk)
+RD_DECLARE_BATCH(bocf)
+#undef RD_DECLARE_BATCH
+
+}  // namespace rd

@@ -65,10 +65,13 @@ template <int MODEL, int STENCIL, int NS, int MODE> struct SweepOccupancy {
       MODE == kModeTangent ? (NS == 4 ? 1 : 2) : (NS == 4 && heavy ? 2 : 3);
 };
 
+// One wavefront's share of a sweep: strip wid % nsx, band wid / nsx of the
+// grid described by c, reading `in` and writing `out` (or the stage inputs
+// `ys`).  Shared by the single-grid and the batched kernels.
 template <int MODEL, int STENCIL, int NS, int MODE>
-__global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
-void sweep_kernel(SweepArgs a) {
+__device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
+                                           double* const (*ys)[kMaxFields], const KConst& c,
+                                           int wid) {
   constexpr bool TAN = MODE == kModeTangent;
   constexpr bool STAGES = MODE == kModeStages;
   constexpr int NV = ModelTraits<MODEL>::NV;
@@ -76,13 +79,10 @@ void sweep_kernel(SweepArgs a) {
   constexpr int ND = TAN ? 2 : 1;        // diffusive components: u (and du)
   constexpr int TX = kWave - 2 * NS;
   constexpr int ZR = (NS + 1 > 3) ? NS + 1 : 3;
-  const KConst& c = a.c;
   auto comp = [](int d) { return d == 0 ? 0 : NV; };  // index of diffusive component d
   auto diffusive = [](int f) { return f == 0 || (TAN && f == NV); };
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (wid >= c.nsx * c.nby) return;  // whole waves only: no barrier follows
   const int sx = wid % c.nsx;
   const int by = wid / c.nsx;
   const int gx = sx * TX - NS + lane;
@@ -126,7 +126,7 @@ void sweep_kernel(SweepArgs a) {
   if (r_first < load_end) {
     const size_t o = (size_t)r_first * nx + cx;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) pre[f] = a.in[f][o];
+    for (int f = 0; f < NF; ++f) pre[f] = in[f][o];
   }
 
   for (int r = r_first; r <= r_last; ++r) {
@@ -156,7 +156,7 @@ void sweep_kernel(SweepArgs a) {
       if (r + 1 < load_end) {
         const size_t o = (size_t)(r + 1) * nx + cx;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) pre[f] = a.in[f][o];
+        for (int f = 0; f < NF; ++f) pre[f] = in[f][o];
       }
     }
 
@@ -206,7 +206,7 @@ void sweep_kernel(SweepArgs a) {
         if (out_col && rho >= yA && rho < yB) {
           const size_t o = (size_t)rho * nx + gx;
 #pragma unroll
-          for (int f = 0; f < NF; ++f) a.out[f][o] = zr[1][f] + c.dt * k[f];
+          for (int f = 0; f < NF; ++f) out[f][o] = zr[1][f] + c.dt * k[f];
         }
         continue;
       }
@@ -226,18 +226,27 @@ void sweep_kernel(SweepArgs a) {
         for (int d = 0; d < ND; ++d) yu[s + 1][0][d] = zr[s][comp(d)] + cs * k[comp(d)];
         if (STAGES && out_col && rho >= yA && rho < yB) {
           const size_t o = (size_t)rho * nx + gx;
-          a.ys[s - 1][0][o] = yu[s + 1][0][0];
+          ys[s - 1][0][o] = yu[s + 1][0][0];
 #pragma unroll
-          for (int f = 1; f < NV; ++f) a.ys[s - 1][f][o] = ygn[s + 1][f];
+          for (int f = 1; f < NV; ++f) ys[s - 1][f][o] = ygn[s + 1][f];
         }
       } else if (!STAGES && out_col && rho >= yA && rho < yB) {
         const double bw = NS == 4 ? c.h6 : c.h2;
         const size_t o = (size_t)rho * nx + gx;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) a.out[f][o] = zr[s][f] + bw * acc[s - 1][f];
+        for (int f = 0; f < NF; ++f) out[f][o] = zr[s][f] + bw * acc[s - 1][f];
       }
     }
   }
+}
+
+template <int MODEL, int STENCIL, int NS, int MODE>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
+void sweep_kernel(SweepArgs a) {
+  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (wid >= a.c.nsx * a.c.nby) return;  // whole waves only: no barrier follows
+  sweep_wave<MODEL, STENCIL, NS, MODE>(a.in, a.out, a.ys, a.c, wid);
 }
 
 template <int MODEL, int STENCIL, int NS, int MODE>
