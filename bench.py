@@ -25,6 +25,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
 FP64_VECTOR_PEAK = 78.6e12  # flop/s, MI355X FP64 vector (FMA = 2 flops)
 KERNEL_SOURCES = ["paper_1309_1720_amd/csrc/rd_device.h", "paper_1309_1720_amd/csrc/rd_sweep.h"]
+# Algorithmic FP64 operations per Fenton-Karma RK4 cell-update, counted from the
+# equations as evaluated (9-point stencil 11, reaction 51 + one exp, stage
+# updates; each add, multiply, divide and exp counts 1).
+FK_RK4_FLOPS = 295
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "fwd_fk_1024_rk4_counters.json")
 
 
@@ -112,6 +116,89 @@ def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
             "timed_steps": steps}
 
 
+def _timed(torch, stream, fn):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def other_workloads(rd, torch, dev):
+    """Timings of the other workloads (rates in cell-updates/s, device time)."""
+    import rd_inputs as ri
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+
+    # Barkley 128^2, 5-point, Euler, 1000 steps (whole run)
+    w = ri.workload("barkley_128_euler")
+    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    p = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=20)
+    rd.step(p, z)
+    p.nsteps = w["nsteps"]
+    sec = _timed(torch, stream, lambda: rd.step(p, z))
+    out["barkley_128_euler_1000"] = {"seconds": sec, "rate": 128 * 128 * w["nsteps"] / sec,
+                                     "us_per_step": sec / w["nsteps"] * 1e6,
+                                     "hbm_frac": 32 * 128 * 128 * w["nsteps"] / sec / HBM_PEAK}
+
+    # Bueno-Orovio 2048^2, anisotropic flux form, RK4 (50 of its 5000 steps)
+    w = ri.workload("bocf_2048_aniso_rk4")
+    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    p = rd.Problem.from_workload(w, ri.params_array("bocf"), nsteps=4)
+    rd.step(p, z)
+    n = 50
+    p.nsteps = n
+    sec = _timed(torch, stream, lambda: rd.step(p, z))
+    cells = w["nx"] * w["ny"]
+    out["bocf_2048_aniso_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
+                                  "hbm_frac": 64 * cells * n / sec / HBM_PEAK}
+
+    # Ensemble: 64 Fenton-Karma grids (16 each of 256^2 .. 768^2) with tangents
+    ws = ri.fk_batch_workloads(nsteps=2)
+    params = ri.params_array("fk")
+    probs = [rd.Problem.from_workload(x, params) for x in ws]
+    fields = [[torch.from_numpy(a).to(dev) for a in ri.fk_ic(x["nx"], x["ny"], x["seed"])] for x in ws]
+    tans = [[torch.from_numpy(a).to(dev) for a in ri.direction(3, x["nx"], x["ny"], x["direction_seed"])]
+            for x in ws]
+    rd.step_batched(probs, fields, tans)      # first calls tune the band height
+    rd.step_batched(probs, fields, None)
+    for q, f, t in zip(probs, fields, tans):
+        rd.jvp(q, f, t)
+    torch.cuda.synchronize()
+    n = 20
+    for q in probs:
+        q.nsteps = n
+    cells = sum(x["nx"] * x["ny"] for x in ws)
+    sec_b = _timed(torch, stream, lambda: rd.step_batched(probs, fields, tans))
+    sec_f = _timed(torch, stream, lambda: rd.step_batched(probs, fields, None))
+
+    def per_instance():
+        for q, f, t in zip(probs, fields, tans):
+            rd.jvp(q, f, t)
+    sec_s = _timed(torch, stream, per_instance)
+    out["fk_ensemble_64_jvp"] = {"steps": n, "cells": cells, "rate_jvp": cells * n / sec_b,
+                                 "rate_forward": cells * n / sec_f, "jvp_over_forward": sec_b / sec_f,
+                                 "per_instance_calls_over_batched": sec_s / sec_b,
+                                 "hbm_frac_jvp": 96 * cells * n / sec_b / HBM_PEAK}
+
+    # Adjoint: Barkley 1024^2, RK4, 4000 steps, checkpoints every 64
+    w = ri.workload("barkley_1024_rk4_adjoint")
+    p = rd.Problem.from_workload(w, ri.params_array("barkley"))
+    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    ck = torch.empty(rd.checkpoint_count(p) * 2 * w["nx"] * w["ny"], dtype=torch.float64, device=dev)
+    sec_fwd = _timed(torch, stream, lambda: rd.step(p, z, ck))
+    lam = [(2.0 * w["dx"] ** 2) * z[0].clone(), torch.zeros_like(z[1])]
+    sec_vjp = _timed(torch, stream, lambda: rd.vjp(p, ck, lam))
+    cells = w["nx"] * w["ny"]
+    out["barkley_1024_rk4_adjoint_4000"] = {
+        "forward_seconds": sec_fwd, "vjp_seconds": sec_vjp, "vjp_over_forward": sec_vjp / sec_fwd,
+        "forward_rate": cells * w["nsteps"] / sec_fwd,
+        "forward_hbm_frac": 32 * cells * w["nsteps"] / sec_fwd / HBM_PEAK}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +208,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jvp", action="store_true")
+    ap.add_argument("--no-other-workloads", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -162,6 +252,15 @@ def main():
     if not all(bool(torch.isfinite(t).all()) for t in z):
         raise RuntimeError("non-finite state after the timed steps")
 
+    tile_rows = rd.get_tile_rows(p, "step")
+    if args.calibration_copy:
+        # a plain elementwise copy of 2^26 doubles (512 MiB read + 512 MiB written)
+        src = torch.rand(1 << 26, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+
     rate = cells * args.steps / sec
     bytes_per_launch = 2 * nv * 8 * cells  # read and write the state once
     launch_s = sec / args.steps            # one fused kernel per step
@@ -187,11 +286,18 @@ def main():
                      "traffic": measured_traffic(cells),
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": launch_s * 1e6},
+        "roofline_alu": {"bound": "alu", "achieved": FK_RK4_FLOPS * rate / 1e12,
+                         "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                         "frac": FK_RK4_FLOPS * rate / FP64_VECTOR_PEAK,
+                         "flops_per_cell_update": FK_RK4_FLOPS},
+        "tile_rows": tile_rows,
         "wall_s": wall,
     }
     if not args.no_jvp:
         out["jvp"] = jvp_report(rd, torch, w, params, z0_np, ms / args.steps,
                                 min(args.steps, 1000), dev)
+    if not args.no_other_workloads:
+        out["other_workloads"] = other_workloads(rd, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, params, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -186,6 +186,11 @@ int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* cons
  * automatic choice).  A performance knob: results do not depend on it. */
 int rd_set_tile_rows(int32_t rows);
 
+/* Band height the library uses for `op` (RD_OP_STEP, RD_OP_JVP, RD_OP_VJP) on
+ * problem `p`: the override, else the autotuner's cached choice, else its
+ * heuristic starting value. */
+int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows);
+
 /* Enables (non-zero, the default) or disables the band-height autotuner.
  * When enabled, the first call for each (operation, model, stencil, scheme,
  * nx, ny) times candidate band heights with HIP events on the caller's stream

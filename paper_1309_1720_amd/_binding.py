@@ -72,6 +72,7 @@ def lib() -> C.CDLL:
             "rd_step_batched": ([P, C.c_int32, C.POINTER(_DPP), C.POINTER(_DPP), _PTR, C.c_size_t, _PTR], C.c_int),
             "rd_set_tile_rows": ([C.c_int32], C.c_int),
             "rd_set_autotune": ([C.c_int32], C.c_int),
+            "rd_get_tile_rows": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rd_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -187,6 +188,14 @@ def checkpoint_count(prob: Problem) -> int:
 def set_tile_rows(rows: int) -> None:
     """Rows per wavefront band for later calls (<= 0: automatic)."""
     _check(lib().rd_set_tile_rows(int(rows)))
+
+
+def get_tile_rows(prob: Problem, op: str = "step") -> int:
+    """Band height the library uses for ``op`` on ``prob`` (see rd_get_tile_rows)."""
+    cp, _buf = prob.to_c()
+    out = C.c_int32(0)
+    _check(lib().rd_get_tile_rows(C.byref(cp), OPS[op], C.byref(out)))
+    return out.value
 
 
 def set_autotune(enable: bool) -> None:

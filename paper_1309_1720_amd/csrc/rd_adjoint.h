@@ -76,7 +76,7 @@ void adjoint_kernel(AdjArgs a) {
   const KConst& c = a.c;
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
   if (wid >= c.nsx * c.nby) return;  // whole waves only: no barrier follows
   const int sx = wid % c.nsx;
   const int by = wid / c.nsx;
@@ -84,6 +84,7 @@ void adjoint_kernel(AdjArgs a) {
   const int cx = min(max(gx, 0), c.nx - 1);
   const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;
   const Column col = make_column(gx, c, false);
+  const bool edge = strip_touches_edge(sx * TX - NS, c);
 
   const int yA = by * c.ty;
   const int yB = min(yA + c.ty, c.ny);
@@ -171,7 +172,8 @@ void adjoint_kernel(AdjArgs a) {
       }
       if (rho == 0) up = kb[0];
       if (rho == c.ny - 1) dn = kb[0];
-      const double lapT = diffusion<STENCIL>(up, kb[0], dn, col, rho, c);
+      const double lapT = edge ? diffusion<STENCIL, true>(up, kb[0], dn, col, rho, c)
+                               : diffusion<STENCIL, false>(up, kb[0], dn, col, rho, c);
 
       double y[NV];
       const size_t o = (size_t)rho * nx + cx;

@@ -70,7 +70,7 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
 
   KConst c;
   derive_constants(p, c);
-  set_geometry(c, ns, heuristic_rows(p->nx, p->ny, ns));
+  set_geometry(c, ns, current_rows(kTuneAdjoint, p->model, p->stencil, p->scheme, p->nx, p->ny, ns));
 
   double* curA[kMaxFields];
   double* curB[kMaxFields];

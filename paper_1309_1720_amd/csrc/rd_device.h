@@ -60,13 +60,14 @@ template <> struct ModelTraits<RD_MODEL_BOCF> { static constexpr int NV = 4; };
 
 // ---------------------------------------------------------------------------
 // Smoothed step: t = kx + 1/2 clamped to [0, 1], H = t^2 (3 - 2t).  Clamping
-// reproduces the 0 and 1 branches exactly (0*0*3 = 0, 1*1*1 = 1).
+// reproduces the 0 and 1 branches exactly (0*0*3 = 0, 1*1*1 = 1).  Used only
+// by the gated models, so it may fuse multiply-adds.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double step_h(double x, const KConst& c) {
   if (c.sharp) return x >= 0.0 ? 1.0 : 0.0;
-  double t = c.k * x + 0.5;
+  double t = fma(c.k, x, 0.5);
   t = fmin(fmax(t, 0.0), 1.0);
-  return t * t * (3.0 - 2.0 * t);
+  return (t * t) * fma(-2.0, t, 3.0);
 }
 
 // H and dH/dx = 6 k t (1 - t) (zero outside the transition and for Heaviside).
@@ -76,9 +77,9 @@ __device__ __forceinline__ void step_h_d(double x, const KConst& c, double& h, d
     dh = 0.0;
     return;
   }
-  double t = c.k * x + 0.5;
+  double t = fma(c.k, x, 0.5);
   t = fmin(fmax(t, 0.0), 1.0);
-  h = t * t * (3.0 - 2.0 * t);
+  h = (t * t) * fma(-2.0, t, 3.0);
   dh = ((6.0 * c.k) * t) * (1.0 - t);
 }
 
@@ -114,10 +115,72 @@ __device__ __forceinline__ Dual operator/(double a, Dual b) {
   return Dual(q, -(q * b.d) / b.v);
 }
 __device__ __forceinline__ Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
-__device__ __forceinline__ double exp(double a) { return ::exp(a); }
+// ---------------------------------------------------------------------------
+// Lean FP64 elementary functions for the reaction terms.
+//
+// exp: Cody-Waite argument reduction x = n ln2 + r, |r| <= ln2/2, with ln2
+// split into a high part whose product with n is exact and a low part, then
+// the Taylor series of e^r to degree 13 (truncation < 1e-17 relative) by
+// Horner's rule in fused multiply-adds, scaled by 2^n.  About 2 ulp; 20 FP64
+// operations against ~40 for the general library routine.
+//
+// recip: the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - d r); within 1 ulp for the positive, finite, normal
+// divisors the reactions use (time constants, 1 + exp(.)).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double exp_lean(double x) {
+  x = fmin(fmax(x, -1.0e4), 1.0e4);  // keeps n in int range; exp saturates far earlier
+  const double n = __builtin_rint(x * 1.4426950408889634);   // log2(e)
+  double r = fma(-n, 6.93147180369123816490e-01, x);        // ln2 high part (exact product)
+  r = fma(-n, 1.90821492927058770002e-10, r);                // ln2 low part
+  double p = 1.0 / 6227020800.0;                             // 1/13!
+  p = fma(p, r, 1.0 / 479001600.0);
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, (int)n);
+}
+
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
+
+__device__ __forceinline__ double exp(double a) { return exp_lean(a); }
 __device__ __forceinline__ Dual exp(Dual a) {
-  const double e = ::exp(a.v);
+  const double e = exp_lean(a.v);
   return Dual(e, e * a.d);
+}
+__device__ __forceinline__ Dual recip(Dual a) {
+  const double r = recip(a.v);
+  return Dual(r, -(r * a.d) * r);
+}
+
+// mad(a, b, c) = a b + c with one rounding (value part identical for double
+// and Dual).
+__device__ __forceinline__ double mad(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ Dual mad(Dual a, double b, Dual c) {
+  return Dual(fma(a.v, b, c.v), fma(a.d, b, c.d));
+}
+__device__ __forceinline__ Dual mad(double a, Dual b, Dual c) {
+  return Dual(fma(a, b.v, c.v), fma(a, b.d, c.d));
+}
+__device__ __forceinline__ Dual mad(Dual a, double b, double c) {
+  return Dual(fma(a.v, b, c), a.d * b);
+}
+__device__ __forceinline__ Dual mad(Dual a, Dual b, Dual c) {
+  return Dual(fma(a.v, b.v, c.v), fma(a.d, b.v, fma(a.v, b.d, c.d)));
 }
 __device__ __forceinline__ Dual step_h(Dual x, const KConst& c) {
   double h, dh;
@@ -131,11 +194,13 @@ __device__ __forceinline__ Dual step_h(Dual x, const KConst& c) {
 // x << 0.
 template <class T>
 __device__ __forceinline__ T half_one_plus_tanh(T x) {
-  return 1.0 / (1.0 + exp(-2.0 * x));
+  return recip(1.0 + exp(-2.0 * x));
 }
 
 // ---------------------------------------------------------------------------
-// Reaction rates f = N(y), every operation rounded as written.
+// Reaction rates f = N(y).  Barkley rounds every operation as written (and so
+// matches the oracle bit for bit); the gated models fuse multiply-adds and
+// multiply by reciprocals of their u-dependent time constants.
 // ---------------------------------------------------------------------------
 template <int MODEL> struct Reaction;
 
@@ -169,13 +234,14 @@ template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
     const T u = y[0], v = y[1], w = y[2];
     const T p = step_h(u - m.u_c, c);
     const T q = step_h(u - m.u_v, c);
+    const T one_p = 1.0 - p;
     const T j_fi = -(((v * p) * (1.0 - u)) * (u - m.u_c)) * m.inv_tau_d;
-    const T j_so = (u * (1.0 - p)) * m.inv_tau_0 + p * m.inv_tau_r;
+    const T j_so = mad(u * one_p, m.inv_tau_0, p * m.inv_tau_r);
     const T j_si = -(w * (2.0 * half_one_plus_tanh(m.k_si * (u - m.u_csi)))) * m.inv_2tau_si;
-    const T tau_vm = q * m.tau_v1m + (1.0 - q) * m.tau_v2m;
+    const T tau_vm = mad(q, m.tau_v1m, (1.0 - q) * m.tau_v2m);
     f[0] = -((j_fi + j_so) + j_si);
-    f[1] = ((1.0 - p) * (1.0 - v)) / tau_vm - (p * v) * m.inv_tau_vp;
-    f[2] = ((1.0 - p) * (1.0 - w)) * m.inv_tau_wm - (p * w) * m.inv_tau_wp;
+    f[1] = mad(-(p * v), m.inv_tau_vp, (one_p * (1.0 - v)) * recip(tau_vm));
+    f[2] = mad(one_p * (1.0 - w), m.inv_tau_wm, -(p * w) * m.inv_tau_wp);
   }
 };
 
@@ -192,24 +258,24 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     const T h_w_neg = step_h(m.th_w - u, c);
     const T h_vm = step_h(u - m.th_vm, c);
     const T h_o = step_h(u - m.th_o, c);
-    const T tau_vm = (1.0 - h_vm) * m.tau_v1m + h_vm * m.tau_v2m;
-    const T tau_wm = m.tau_w1m + m.dtau_wm * half_one_plus_tanh(m.k_wm * (u - m.u_wm));
-    const T tau_so = m.tau_so1 + m.dtau_so * half_one_plus_tanh(m.k_so * (u - m.u_so));
-    const T tau_s = (1.0 - h_w) * m.tau_s1 + h_w * m.tau_s2;
-    const T tau_o = (1.0 - h_o) * m.tau_o1 + h_o * m.tau_o2;
+    const T r_vm = recip(mad(1.0 - h_vm, m.tau_v1m, h_vm * m.tau_v2m));           // 1/tau_v^-
+    const T r_wm = recip(mad(m.dtau_wm, half_one_plus_tanh(m.k_wm * (u - m.u_wm)), T(m.tau_w1m)));
+    const T r_so = recip(mad(m.dtau_so, half_one_plus_tanh(m.k_so * (u - m.u_so)), T(m.tau_so1)));
+    const T r_s = recip(mad(1.0 - h_w, m.tau_s1, h_w * m.tau_s2));                 // 1/tau_s
+    const T r_o = recip(mad(1.0 - h_o, m.tau_o1, h_o * m.tau_o2));                 // 1/tau_o
     const T v_inf = step_h(m.th_vm - u, c);
-    const T w_inf = (1.0 - h_o) * (1.0 - u * m.inv_tau_winf) + h_o * m.w_infstar;
+    const T w_inf = mad(1.0 - h_o, mad(-u, m.inv_tau_winf, 1.0), h_o * m.w_infstar);
     const T j_fi = -(((v * h_v) * (u - m.th_v)) * (m.u_u - u)) * m.inv_tau_fi;
-    const T j_so = ((u - m.u_o) * h_w_neg) / tau_o + h_w / tau_so;
+    const T j_so = mad((u - m.u_o) * h_w_neg, r_o, h_w * r_so);
     const T j_si = -((h_w * w) * s) * m.inv_tau_si;
     f[0] = -((j_fi + j_so) + j_si);
-    const T alpha_v = -(h_v * m.inv_tau_vp) - h_v_neg / tau_vm;
-    const T beta_v = (h_v_neg * v_inf) / tau_vm;
-    f[1] = alpha_v * v + beta_v;
-    const T alpha_w = -(h_w * m.inv_tau_wp) - h_w_neg / tau_wm;
-    const T beta_w = (h_w_neg * w_inf) / tau_wm;
-    f[2] = alpha_w * w + beta_w;
-    f[3] = (half_one_plus_tanh(m.k_s * (u - m.u_s)) - s) / tau_s;
+    const T alpha_v = mad(-h_v, m.inv_tau_vp, -(h_v_neg * r_vm));
+    const T beta_v = (h_v_neg * v_inf) * r_vm;
+    f[1] = mad(alpha_v, v, beta_v);
+    const T alpha_w = mad(-h_w, m.inv_tau_wp, -(h_w_neg * r_wm));
+    const T beta_w = (h_w_neg * w_inf) * r_wm;
+    f[2] = mad(alpha_w, w, beta_w);
+    f[3] = (half_one_plus_tanh(m.k_s * (u - m.u_s)) - s) * r_s;
   }
 };
 
@@ -249,6 +315,12 @@ struct Column {
   double dxx_e, dxy_e4, dxy_c4, dyy_c;  // anisotropic tensor at face gx+1/2 / centre gx
 };
 
+// Whether the 64 columns of the strip starting at column x0 include the first
+// or the last column of the grid (wave-uniform).
+__device__ __forceinline__ bool strip_touches_edge(int x0, const KConst& c) {
+  return x0 <= 0 || x0 + kWave - 1 >= c.nx - 1;
+}
+
 __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool aniso) {
   Column col;
   col.gx = gx;
@@ -271,21 +343,22 @@ __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool anis
 // Diffusion term at row `rho` of this lane's column, given the values `up`
 // (row rho-1), `cen` (row rho) and `dn` (row rho+1), already mirrored in y
 // (up = cen at rho = 0, dn = cen at rho = ny-1).  All lanes of the wave must
-// call it together (cross-lane reads).
-template <int STENCIL>
+// call it together (cross-lane reads).  EDGE: some lane of this wave holds
+// the first or last column of the grid, so x-mirrors must be applied.
+template <int STENCIL, bool EDGE>
 __device__ __forceinline__ double diffusion(double up, double cen, double dn, const Column& col,
                                             int rho, const KConst& c) {
   if constexpr (STENCIL == RD_LAP5) {
     double w = from_west(cen), e = from_east(cen);
-    if (col.west) w = cen;
-    if (col.east) e = cen;
+    if (EDGE && col.west) w = cen;
+    if (EDGE && col.east) e = cen;
     return c.cD * (((w + e) + (up + dn)) - 4.0 * cen);
   } else if constexpr (STENCIL == RD_LAP9) {
     const double cs = up + dn;  // N + S of this column
     double w = from_west(cen), e = from_east(cen);
     double ws = from_west(cs), es = from_east(cs);  // NW + SW, NE + SE
-    if (col.west) { w = cen; ws = cs; }
-    if (col.east) { e = cen; es = cs; }
+    if (EDGE && col.west) { w = cen; ws = cs; }
+    if (EDGE && col.east) { e = cen; es = cs; }
     const double axial = ((w + e) + cs) - 4.0 * cen;
     const double diag = (ws + es) - 4.0 * cen;
     return c.cD * (kAlphaAxial * axial + kAlphaDiag * diag);
@@ -297,12 +370,13 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
     const double wU = from_west(up), eU = from_east(up);
     const double wD = from_west(dn), eD = from_east(dn);
     double fxe = col.dxx_e * (eC - cen) + col.dxy_e4 * ((eD + dn) - (eU + up));
-    if (col.east) fxe = 0.0;
+    if (EDGE && col.east) fxe = 0.0;
     double fxw = from_west(fxe);
-    if (col.west) fxw = 0.0;
-    const double wCc = col.west ? cen : wC, eCc = col.east ? cen : eC;
-    const double wUc = col.west ? up : wU, eUc = col.east ? up : eU;
-    const double wDc = col.west ? dn : wD, eDc = col.east ? dn : eD;
+    if (EDGE && col.west) fxw = 0.0;
+    const bool mw = EDGE && col.west, me = EDGE && col.east;
+    const double wCc = mw ? cen : wC, eCc = me ? cen : eC;
+    const double wUc = mw ? up : wU, eUc = me ? up : eU;
+    const double wDc = mw ? dn : wD, eDc = me ? dn : eD;
     double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (dn - cen);
     double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (cen - up);
     if (rho == c.ny - 1) fys = 0.0;

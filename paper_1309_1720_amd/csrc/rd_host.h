@@ -21,6 +21,8 @@ void set_geometry(KConst& c, int ns, int ty);
 // launch with that band height that writes only workspace.
 enum TuneKind { kTuneForward = 0, kTuneTangent = 1, kTuneAdjoint = 2, kTuneBatched = 3 };
 int heuristic_rows(int nx, int ny, int ns);
+// Override, else cached tuning result, else heuristic (never tunes).
+int current_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns);
 int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns,
                hipStream_t s, const std::function<hipError_t(int)>& trial);
 size_t align_up(size_t x, size_t a);

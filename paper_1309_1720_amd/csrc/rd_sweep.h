@@ -68,10 +68,10 @@ template <int MODEL, int STENCIL, int NS, int MODE> struct SweepOccupancy {
 // One wavefront's share of a sweep: strip wid % nsx, band wid / nsx of the
 // grid described by c, reading `in` and writing `out` (or the stage inputs
 // `ys`).  Shared by the single-grid and the batched kernels.
-template <int MODEL, int STENCIL, int NS, int MODE>
-__device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
-                                           double* const (*ys)[kMaxFields], const KConst& c,
-                                           int wid) {
+template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE>
+__device__ __forceinline__ void sweep_wave_impl(const double* const* in, double* const* out,
+                                                double* const (*ys)[kMaxFields], const KConst& c,
+                                                int wid) {
   constexpr bool TAN = MODE == kModeTangent;
   constexpr bool STAGES = MODE == kModeStages;
   constexpr int NV = ModelTraits<MODEL>::NV;
@@ -196,7 +196,7 @@ __device__ __forceinline__ void sweep_wave(const double* const* in, double* cons
 
       double lap[ND];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) lap[d] = diffusion<STENCIL>(up[d], y[comp(d)], dn[d], col, rho, c);
+      for (int d = 0; d < ND; ++d) lap[d] = diffusion<STENCIL, EDGE>(up[d], y[comp(d)], dn[d], col, rho, c);
       double k[NF];
       eval_rates<MODEL, TAN>(c, y, k);
 #pragma unroll
@@ -240,11 +240,23 @@ __device__ __forceinline__ void sweep_wave(const double* const* in, double* cons
   }
 }
 
+// Strips that touch the grid's x-edges apply the mirror; interior strips skip it.
+template <int MODEL, int STENCIL, int NS, int MODE>
+__device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
+                                           double* const (*ys)[kMaxFields], const KConst& c,
+                                           int wid) {
+  const int x0 = (wid % c.nsx) * (kWave - 2 * NS) - NS;
+  if (strip_touches_edge(x0, c))
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true>(in, out, ys, c, wid);
+  else
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false>(in, out, ys, c, wid);
+}
+
 template <int MODEL, int STENCIL, int NS, int MODE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
 void sweep_kernel(SweepArgs a) {
-  const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
   if (wid >= a.c.nsx * a.c.nby) return;  // whole waves only: no barrier follows
   sweep_wave<MODEL, STENCIL, NS, MODE>(a.in, a.out, a.ys, a.c, wid);
 }

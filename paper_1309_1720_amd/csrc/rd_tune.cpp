@@ -91,9 +91,33 @@ int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int
   return best;
 }
 
+int current_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_override > 0) return g_override < ny ? g_override : ny;
+  auto it = g_cache.find(std::make_tuple(kind, model, stencil, scheme, nx, ny));
+  if (it != g_cache.end()) return it->second;
+  return heuristic_rows(nx, ny, ns);
+}
+
 }  // namespace rd
 
 extern "C" {
+
+int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows) {
+  int rc = rd::validate(p);
+  if (rc) return rc;
+  if (!rows) return rd::fail(RD_EINVAL, "rows is NULL");
+  int kind;
+  switch (op) {
+    case RD_OP_STEP: kind = rd::kTuneForward; break;
+    case RD_OP_JVP: kind = rd::kTuneTangent; break;
+    case RD_OP_VJP: kind = rd::kTuneAdjoint; break;
+    default: return rd::fail(RD_EINVAL, "rd_get_tile_rows: op %d has no single-grid band height", op);
+  }
+  const int ns = rd::n_stages(p->scheme);
+  *rows = rd::current_rows(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns);
+  return RD_OK;
+}
 
 int rd_set_tile_rows(int32_t rows) {
   rd::set_tile_rows_override(rows);
