@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--variant", choices=["sweep", "pipe"], default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jvp", action="store_true")
@@ -232,6 +233,8 @@ def main():
     z = [torch.from_numpy(a).to(dev) for a in z0_np]
     if args.tile_rows:
         rd.set_tile_rows(args.tile_rows)
+    if args.variant:
+        rd.set_kernel_variant(args.variant)
     p = rd.Problem.from_workload(w, params, nsteps=args.warmup)
     if args.warmup:
         rd.step(p, z)
@@ -252,7 +255,7 @@ def main():
     if not all(bool(torch.isfinite(t).all()) for t in z):
         raise RuntimeError("non-finite state after the timed steps")
 
-    tile_rows = rd.get_tile_rows(p, "step")
+    variant, tile_rows = rd.get_plan(p, "step")
     if args.calibration_copy:
         # a plain elementwise copy of 2^26 doubles (512 MiB read + 512 MiB written)
         src = torch.rand(1 << 26, dtype=torch.float64, device=dev)
@@ -290,6 +293,7 @@ def main():
                          "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                          "frac": FK_RK4_FLOPS * rate / FP64_VECTOR_PEAK,
                          "flops_per_cell_update": FK_RK4_FLOPS},
+        "kernel_variant": variant,
         "tile_rows": tile_rows,
         "wall_s": wall,
     }

@@ -186,6 +186,17 @@ int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* cons
  * automatic choice).  A performance knob: results do not depend on it. */
 int rd_set_tile_rows(int32_t rows);
 
+/* Fixes the fused-step kernel variant for later calls: 0 = one wavefront
+ * carrying every stage of a step, 1 = one wavefront per stage (stage-
+ * pipelined workgroup); negative = chosen by the autotuner (default).  A
+ * performance knob: both variants produce identical bits. */
+int rd_set_kernel_variant(int32_t variant);
+
+/* Kernel variant and band height the library uses for `op` (RD_OP_STEP or
+ * RD_OP_JVP) on problem `p` (overrides, else the tuned choice, else the
+ * heuristic starting plan). */
+int rd_get_plan(const rd_problem* p, int32_t op, int32_t* variant, int32_t* rows);
+
 /* Band height the library uses for `op` (RD_OP_STEP, RD_OP_JVP, RD_OP_VJP) on
  * problem `p`: the override, else the autotuner's cached choice, else its
  * heuristic starting value. */

@@ -73,6 +73,8 @@ def lib() -> C.CDLL:
             "rd_set_tile_rows": ([C.c_int32], C.c_int),
             "rd_set_autotune": ([C.c_int32], C.c_int),
             "rd_get_tile_rows": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+            "rd_set_kernel_variant": ([C.c_int32], C.c_int),
+            "rd_get_plan": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "rd_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -196,6 +198,22 @@ def get_tile_rows(prob: Problem, op: str = "step") -> int:
     out = C.c_int32(0)
     _check(lib().rd_get_tile_rows(C.byref(cp), OPS[op], C.byref(out)))
     return out.value
+
+
+VARIANTS = {"sweep": 0, "pipe": 1}
+
+
+def set_kernel_variant(variant) -> None:
+    """Fix the fused-step kernel ("sweep", "pipe") or None for the autotuner."""
+    _check(lib().rd_set_kernel_variant(-1 if variant is None else VARIANTS[variant]))
+
+
+def get_plan(prob: Problem, op: str = "step"):
+    """(kernel variant name, rows per band) used for ``op`` on ``prob``."""
+    cp, _buf = prob.to_c()
+    v, r = C.c_int32(0), C.c_int32(0)
+    _check(lib().rd_get_plan(C.byref(cp), OPS[op], C.byref(v), C.byref(r)))
+    return {0: "sweep", 1: "pipe"}[v.value], r.value
 
 
 def set_autotune(enable: bool) -> None:

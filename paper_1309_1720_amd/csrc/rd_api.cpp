@@ -204,13 +204,17 @@ size_t field_bytes(const rd_problem* p) {
 
 hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const SweepArgs& a,
                              hipStream_t s) {
-#define RD_MODE_SWITCH(name)                                              \
-  switch (mode) {                                                         \
-    case kModeStep: return launch_sweep_fwd_##name(stencil, scheme, a, s); \
-    case kModeTangent: return launch_sweep_tan_##name(stencil, scheme, a, s); \
-    case kModeStages: return launch_sweep_stg_##name(stencil, scheme, a, s); \
-  }                                                                       \
+#define RD_MODE_SWITCH(name)                                                                       \
+  switch (mode) {                                                                                  \
+    case kModeStep:                                                                                \
+      return pipe ? launch_pipe_fwd_##name(stencil, scheme, a, s) : launch_sweep_fwd_##name(stencil, scheme, a, s); \
+    case kModeTangent:                                                                             \
+      return pipe ? launch_pipe_tan_##name(stencil, scheme, a, s) : launch_sweep_tan_##name(stencil, scheme, a, s); \
+    case kModeStages:                                                                              \
+      return pipe ? launch_pipe_stg_##name(stencil, scheme, a, s) : launch_sweep_stg_##name(stencil, scheme, a, s); \
+  }                                                                                                \
   break;
+  const bool pipe = a.c.variant == kVariantPipe;
   switch (model) {
     case RD_MODEL_DIFFUSION: RD_MODE_SWITCH(diffusion)
     case RD_MODEL_BARKLEY: RD_MODE_SWITCH(barkley)
@@ -279,20 +283,22 @@ void plan_geometry(const rd_problem* p, KConst& c, bool tangent, double* const* 
                    double* const* out, hipStream_t s) {
   const int ns = n_stages(p->scheme);
   const int np = (tangent ? 2 : 1) * n_fields(p->model);
-  auto trial = [&](int ty) {
+  auto trial = [&](Plan pl) {
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     a.c = c;
-    set_geometry(a.c, ns, ty);
+    a.c.variant = pl.variant;
+    set_geometry(a.c, ns, pl.ty);
     for (int f = 0; f < np; ++f) {
       a.in[f] = in[f];
       a.out[f] = out[f];
     }
     return launch_sweep_mode(tangent ? kModeTangent : kModeStep, p->model, p->stencil, p->scheme, a, s);
   };
-  const int ty = tuned_rows(tangent ? kTuneTangent : kTuneForward, p->model, p->stencil, p->scheme,
-                            p->nx, p->ny, ns, s, trial);
-  set_geometry(c, ns, ty);
+  const Plan pl = tuned_plan(tangent ? kTuneTangent : kTuneForward, p->model, p->stencil, p->scheme,
+                             p->nx, p->ny, ns, s, trial, true);
+  c.variant = pl.variant;
+  set_geometry(c, ns, pl.ty);
 }
 
 int check_workspace(void* ws, size_t ws_bytes, size_t need) {

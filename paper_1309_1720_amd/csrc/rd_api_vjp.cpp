@@ -70,6 +70,12 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
 
   KConst c;
   derive_constants(p, c);
+  // recompute and stage-input launches use the forward step's plan; the
+  // adjoint kernel its own band height
+  const Plan fp = current_plan(kTuneForward, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true);
+  KConst cf = c;
+  cf.variant = fp.variant;
+  set_geometry(cf, ns, fp.ty);
   set_geometry(c, ns, current_rows(kTuneAdjoint, p->model, p->stencil, p->scheme, p->nx, p->ny, ns));
 
   double* curA[kMaxFields];
@@ -97,7 +103,7 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
     for (int64_t n = start + 1; n < stop; ++n) {
       SweepArgs a;
       std::memset(&a, 0, sizeof a);
-      a.c = c;
+      a.c = cf;
       for (int f = 0; f < nv; ++f) {
         a.in[f] = state(n - 1, f);
         a.out[f] = state(n, f);
@@ -109,7 +115,7 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
       if (ns > 1) {
         SweepArgs a;
         std::memset(&a, 0, sizeof a);
-        a.c = c;
+        a.c = cf;
         for (int f = 0; f < nv; ++f) a.in[f] = state(n, f);
         for (int i = 0; i < ns - 1; ++i)
           for (int f = 0; f < nv; ++f) a.ys[i][f] = stage_in(i, f);

@@ -44,6 +44,7 @@ struct KConst {
   int nx, ny;        // grid
   int nsx, nby, ty;  // launch geometry: column strips, row bands, rows per band
   int sharp;         // 1: Heaviside step instead of H_k
+  int variant;       // fused-step kernel variant (StepVariant)
   double k;          // H_k sharpness
   double dt, h2, h6; // dt, dt/2, dt/6
   double cD;         // D_par / dx^2 (isotropic stencils)
@@ -313,6 +314,7 @@ struct Column {
   bool west;     // gx <= 0: west neighbour is the mirror ghost (this column)
   bool east;     // gx >= nx-1: east neighbour is the mirror ghost
   double dxx_e, dxy_e4, dxy_c4, dyy_c;  // anisotropic tensor at face gx+1/2 / centre gx
+  double dxx_w, dxy_w4;                 // ... at face gx-1/2, as the west neighbour computes it
 };
 
 // Whether the 64 columns of the strip starting at column x0 include the first
@@ -326,14 +328,18 @@ __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool anis
   col.gx = gx;
   col.west = gx <= 0;
   col.east = gx >= c.nx - 1;
-  col.dxx_e = col.dxy_e4 = col.dxy_c4 = col.dyy_c = 0.0;
+  col.dxx_e = col.dxy_e4 = col.dxy_c4 = col.dyy_c = col.dxx_w = col.dxy_w4 = 0.0;
   if (aniso) {
-    const double g = (double)gx;
+    const double g = (double)gx, gw = (double)(gx - 1);
     const double th_f = c.theta0 + c.dtheta * ((g + 1.0) / c.n_total);
+    const double th_w = c.theta0 + c.dtheta * ((gw + 1.0) / c.n_total);
     const double th_c = c.theta0 + c.dtheta * ((g + 0.5) / c.n_total);
     const double cf = cos(th_f), sf = sin(th_f), cc = cos(th_c), sc = sin(th_c);
+    const double cw = cos(th_w), sw = sin(th_w);
     col.dxx_e = c.d_perp + (c.dd * cf) * cf;
     col.dxy_e4 = 0.25 * ((c.dd * cf) * sf);
+    col.dxx_w = c.d_perp + (c.dd * cw) * cw;
+    col.dxy_w4 = 0.25 * ((c.dd * cw) * sw);
     col.dxy_c4 = 0.25 * ((c.dd * cc) * sc);
     col.dyy_c = c.d_perp + (c.dd * sc) * sc;
   }
@@ -379,6 +385,41 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
     const double wDc = mw ? dn : wD, eDc = me ? dn : eD;
     double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (dn - cen);
     double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (cen - up);
+    if (rho == c.ny - 1) fys = 0.0;
+    if (rho == 0) fyn = 0.0;
+    return ((fxe - fxw) + (fys - fyn)) * c.inv_dx2;
+  }
+}
+
+// The same operators with the three rows read from LDS.  Row arrays hold one
+// value per lane at index lane + 1 (a pad column on each side); il is this
+// lane's index, iw / ie the west / east neighbours after the x-mirror (equal
+// to il where the neighbour is a ghost).  The arithmetic and its operand
+// order are those of `diffusion`, so both give identical bits; the west
+// x-face flux is recomputed here exactly as the west neighbour computes its
+// east x-face flux.
+template <int STENCIL, bool EDGE>
+__device__ __forceinline__ double diffusion_rows(const double* up, const double* cen, const double* dn,
+                                                 int il, int iw, int ie, const Column& col, int rho,
+                                                 const KConst& c) {
+  const double C = cen[il];
+  if constexpr (STENCIL == RD_LAP5) {
+    return c.cD * (((cen[iw] + cen[ie]) + (up[il] + dn[il])) - 4.0 * C);
+  } else if constexpr (STENCIL == RD_LAP9) {
+    const double cs = up[il] + dn[il];
+    const double ws = up[iw] + dn[iw], es = up[ie] + dn[ie];
+    const double axial = ((cen[iw] + cen[ie]) + cs) - 4.0 * C;
+    const double diag = (ws + es) - 4.0 * C;
+    return c.cD * (kAlphaAxial * axial + kAlphaDiag * diag);
+  } else {
+    const double u = up[il], d = dn[il];
+    double fxe = col.dxx_e * (cen[il + 1] - C) + col.dxy_e4 * ((dn[il + 1] + d) - (up[il + 1] + u));
+    if (EDGE && col.east) fxe = 0.0;
+    double fxw = col.dxx_w * (C - cen[il - 1]) + col.dxy_w4 * ((d + dn[il - 1]) - (u + up[il - 1]));
+    if (EDGE && col.west) fxw = 0.0;
+    const double wCc = cen[iw], eCc = cen[ie], wUc = up[iw], eUc = up[ie], wDc = dn[iw], eDc = dn[ie];
+    double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (d - C);
+    double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (C - u);
     if (rho == c.ny - 1) fys = 0.0;
     if (rho == 0) fyn = 0.0;
     return ((fxe - fxw) + (fys - fyn)) * c.inv_dx2;

@@ -20,6 +20,15 @@ void set_geometry(KConst& c, int ns, int ty);
 // Autotuned rows per wave band (rd_tune.cpp).  `trial(ty)` enqueues one
 // launch with that band height that writes only workspace.
 enum TuneKind { kTuneForward = 0, kTuneTangent = 1, kTuneAdjoint = 2, kTuneBatched = 3 };
+struct Plan {
+  int variant;  // StepVariant
+  int ty;       // rows per band
+};
+// Tunes kernel variant and band height together (trial launches write only
+// workspace); allow_pipe = false restricts to the sweep kernel.
+Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
+                const std::function<hipError_t(Plan)>& trial, bool allow_pipe);
+Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe);
 int heuristic_rows(int nx, int ny, int ns);
 // Override, else cached tuning result, else heuristic (never tunes).
 int current_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns);

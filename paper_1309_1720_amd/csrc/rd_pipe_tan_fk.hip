@@ -1,0 +1,8 @@
+// Stage-pipelined fused-step kernels of the fk model advancing the state and a tangent, all stencils and schemes.
+#include "rd_pipe.h"
+
+namespace rd {
+hipError_t launch_pipe_tan_fk(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
+  return launch_pipe_model<RD_MODEL_FENTON_KARMA, kModeTangent>(stencil, scheme, a, stream);
+}
+}  // namespace rd

@@ -313,6 +313,25 @@ RD_DECLARE_SWEEP(stg, barkley)
 RD_DECLARE_SWEEP(stg, fk)
 RD_DECLARE_SWEEP(stg, bocf)
 #undef RD_DECLARE_SWEEP
+#define RD_DECLARE_PIPE(kind, model) \
+  hipError_t launch_pipe_##kind##_##model(int stencil, int scheme, const SweepArgs& a, hipStream_t s);
+RD_DECLARE_PIPE(fwd, diffusion)
+RD_DECLARE_PIPE(fwd, barkley)
+RD_DECLARE_PIPE(fwd, fk)
+RD_DECLARE_PIPE(fwd, bocf)
+RD_DECLARE_PIPE(tan, diffusion)
+RD_DECLARE_PIPE(tan, barkley)
+RD_DECLARE_PIPE(tan, fk)
+RD_DECLARE_PIPE(tan, bocf)
+RD_DECLARE_PIPE(stg, diffusion)
+RD_DECLARE_PIPE(stg, barkley)
+RD_DECLARE_PIPE(stg, fk)
+RD_DECLARE_PIPE(stg, bocf)
+#undef RD_DECLARE_PIPE
+
+// Kernel variants of the fused step (identical results): one wave carrying
+// every stage (rd_sweep.h) or one wave per stage (rd_pipe.h).
+enum StepVariant { kVariantSweep = 0, kVariantPipe = 1 };
 
 // Dispatch over models.
 hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const SweepArgs& a,

@@ -13,19 +13,26 @@
 #include <vector>
 
 #include "rd_host.h"
+#include "rd_sweep.h"
 
 namespace rd {
 
 namespace {
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, int, int>, int> g_cache;
+std::map<std::tuple<int, int, int, int, int, int>, Plan> g_cache;
 bool g_enabled = true;
-int g_override = -1;
+int g_override = -1;          // rows per band (> 0: fixed)
+int g_variant_override = -1;  // kernel variant (>= 0: fixed)
 }  // namespace
 
 void set_tile_rows_override(int rows) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_override = rows;
+}
+
+void set_variant_override(int variant) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_variant_override = variant;
 }
 
 void set_autotune(bool on) {
@@ -43,28 +50,54 @@ int heuristic_rows(int nx, int ny, int ns) {
   return ty < ny ? ty : ny;
 }
 
-int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns,
-               hipStream_t s, const std::function<hipError_t(int)>& trial) {
+// Starting plan without measurements: the pipelined kernel with bands sized
+// for about 640 workgroups, or the sweep kernel when the variant is fixed to it.
+static Plan heuristic_plan(int nx, int ny, int ns, int variant) {
+  if (variant == kVariantSweep) return Plan{kVariantSweep, heuristic_rows(nx, ny, ns)};
+  const int tx = 64 - 2 * ns;
+  const int nsx = (nx + tx - 1) / tx;
+  const int nby = (640 + nsx - 1) / nsx;
+  int ty = (ny + nby - 1) / nby;
+  if (ty < 4 * ns) ty = 4 * ns;
+  return Plan{kVariantPipe, ty < ny ? ty : ny};
+}
+
+static Plan apply_overrides(Plan p, int ny) {
+  if (g_variant_override >= 0) p.variant = g_variant_override;
+  if (g_override > 0) p.ty = g_override < ny ? g_override : ny;
+  return p;
+}
+
+Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
+                const std::function<hipError_t(Plan)>& trial, bool allow_pipe) {
   const auto key = std::make_tuple(kind, model, stencil, scheme, nx, ny);
-  const int fallback = heuristic_rows(nx, ny, ns);
+  bool tune;
+  Plan fallback;
+  std::vector<Plan> cands;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_override > 0) return g_override < ny ? g_override : ny;
+    const int vfix = allow_pipe ? g_variant_override : kVariantSweep;
+    fallback = apply_overrides(heuristic_plan(nx, ny, ns, vfix), ny);
+    if (!allow_pipe) fallback.variant = kVariantSweep;
+    if (g_override > 0 && vfix >= 0) return fallback;  // fully fixed
     auto it = g_cache.find(key);
     if (it != g_cache.end()) return it->second;
-    if (!g_enabled) return fallback;
+    tune = g_enabled;
+    if (vfix != kVariantPipe)
+      for (int ty : {2, 3, 4, 6, 8, 10, 12, 16, 24})
+        if (ty <= ny && ty >= ns && (g_override <= 0 || ty == fallback.ty)) cands.push_back(Plan{kVariantSweep, ty});
+    if (allow_pipe && vfix != kVariantSweep)
+      for (int ty : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96})
+        if (ty <= ny && ty >= ns && (g_override <= 0 || ty == fallback.ty)) cands.push_back(Plan{kVariantPipe, ty});
   }
+  if (!tune) return fallback;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
     return fallback;  // no timing inside a graph capture
-
-  std::vector<int> cands;
-  for (int ty : {2, 3, 4, 6, 8, 10, 12, 16, 24, 32, 48, 64})
-    if (ty <= ny && ty >= ns) cands.push_back(ty);
-  if (cands.empty()) cands.push_back(ny);
+  if (cands.empty()) cands.push_back(fallback);
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  int best = fallback;
+  Plan best = fallback;
   bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   if (ok) ok = trial(fallback) == hipSuccess;  // warm-up
   float best_ms = 1e30f;
@@ -91,17 +124,51 @@ int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int
   return best;
 }
 
-int current_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns) {
+int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
+               const std::function<hipError_t(int)>& trial) {
+  return tuned_plan(kind, model, stencil, scheme, nx, ny, ns, s,
+                    [&](Plan p) { return trial(p.ty); }, false).ty;
+}
+
+Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (g_override > 0) return g_override < ny ? g_override : ny;
   auto it = g_cache.find(std::make_tuple(kind, model, stencil, scheme, nx, ny));
   if (it != g_cache.end()) return it->second;
-  return heuristic_rows(nx, ny, ns);
+  Plan p = apply_overrides(heuristic_plan(nx, ny, ns, allow_pipe ? g_variant_override : kVariantSweep), ny);
+  if (!allow_pipe) p.variant = kVariantSweep;
+  return p;
+}
+
+int current_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns) {
+  return current_plan(kind, model, stencil, scheme, nx, ny, ns, false).ty;
 }
 
 }  // namespace rd
 
 extern "C" {
+
+int rd_set_kernel_variant(int32_t variant) {
+  if (variant > rd::kVariantPipe) return rd::fail(RD_EINVAL, "unknown kernel variant %d", variant);
+  rd::set_variant_override(variant < 0 ? -1 : variant);
+  return RD_OK;
+}
+
+int rd_get_plan(const rd_problem* p, int32_t op, int32_t* variant, int32_t* rows) {
+  int rc = rd::validate(p);
+  if (rc) return rc;
+  if (!rows || !variant) return rd::fail(RD_EINVAL, "output pointer is NULL");
+  int kind;
+  switch (op) {
+    case RD_OP_STEP: kind = rd::kTuneForward; break;
+    case RD_OP_JVP: kind = rd::kTuneTangent; break;
+    default: return rd::fail(RD_EINVAL, "rd_get_plan: op %d has no single-grid plan", op);
+  }
+  const rd::Plan pl = rd::current_plan(kind, p->model, p->stencil, p->scheme, p->nx, p->ny,
+                                       rd::n_stages(p->scheme), true);
+  *variant = pl.variant;
+  *rows = pl.ty;
+  return RD_OK;
+}
 
 int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows) {
   int rc = rd::validate(p);
@@ -115,7 +182,8 @@ int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows) {
     default: return rd::fail(RD_EINVAL, "rd_get_tile_rows: op %d has no single-grid band height", op);
   }
   const int ns = rd::n_stages(p->scheme);
-  *rows = rd::current_rows(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns);
+  *rows = op == RD_OP_VJP ? rd::current_rows(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns)
+                          : rd::current_plan(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true).ty;
   return RD_OK;
 }
 

@@ -33,20 +33,49 @@ def initial(model, w):
     return ri.initial_condition(w)
 
 
+@pytest.fixture
+def variant(request):
+    rd.set_kernel_variant(request.param)
+    yield request.param
+    rd.set_kernel_variant(None)
+
+
+@pytest.mark.parametrize("variant", ["sweep", "pipe"], indirect=True)
 @pytest.mark.parametrize("model,stencil,scheme", COMBOS)
-def test_every_combination_matches_oracle(model, stencil, scheme):
-    """131 x 77: three strips with a ragged tail in x, several bands in y."""
+def test_every_combination_matches_oracle(model, stencil, scheme, variant):
+    """131 x 77: three strips with a ragged tail in x, several bands in y;
+    both kernel variants."""
     w = workload(model, stencil, scheme, 131, 77)
     po, pr = problems(w, nsteps=37)
     z0 = initial(model, w)
     ref = oracle.step(po, z0, 37)
     got = gpu_step(pr, z0)
     err = rel_linf(got, ref)
-    print(f"{model} {stencil} {scheme}: rel-Linf {err:.3e}")
+    print(f"{variant} {model} {stencil} {scheme}: rel-Linf {err:.3e}")
     assert err <= TOL
     if model in ("diffusion", "barkley") and stencil != "lap9_aniso":
         # same operations in the same order, no library math: bit-identical
         assert all(np.array_equal(g, r) for g, r in zip(got, ref))
+
+
+@pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rk4"), ("bocf", "lap9_aniso", "rk4"),
+                                                  ("barkley", "lap5", "euler"), ("fk", "lap5", "heun")])
+def test_kernel_variants_and_band_heights_agree_bitwise(model, stencil, scheme):
+    w = workload(model, stencil, scheme, 190, 97)
+    _, pr = problems(w, nsteps=5)
+    z0 = ri.random_fields(model, 190, 97, 31)
+    outs = []
+    try:
+        for v in ("sweep", "pipe"):
+            rd.set_kernel_variant(v)
+            for rows in (1, 4, 13, 97):
+                rd.set_tile_rows(rows)
+                outs.append(gpu_step(pr, z0))
+    finally:
+        rd.set_kernel_variant(None)
+        rd.set_tile_rows(0)
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
 
 
 @pytest.mark.parametrize("name,model,n,steps", [
@@ -82,10 +111,11 @@ def test_full_size_sampled_windows(name, steps):
         assert err <= TOL, (x0, y0, err)
 
 
+@pytest.mark.parametrize("variant", ["sweep", "pipe"], indirect=True)
 @pytest.mark.parametrize("nx,ny", [(1, 1), (1, 9), (9, 1), (2, 2), (3, 130), (130, 3), (57, 5), (56, 56)])
 @pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rk4"), ("barkley", "lap5", "heun"),
                                                   ("bocf", "lap9_aniso", "euler")])
-def test_degenerate_and_ragged_grids(nx, ny, model, stencil, scheme):
+def test_degenerate_and_ragged_grids(nx, ny, model, stencil, scheme, variant):
     w = workload(model, stencil, scheme, nx, ny)
     po, pr = problems(w, nsteps=5)
     z0 = ri.random_fields(model, nx, ny, 17)

@@ -32,8 +32,16 @@ def gpu_jvp(pr, z0, v):
     return host(zt), host(vt)
 
 
+@pytest.fixture
+def variant(request):
+    rd.set_kernel_variant(request.param)
+    yield request.param
+    rd.set_kernel_variant(None)
+
+
+@pytest.mark.parametrize("variant", ["sweep", "pipe"], indirect=True)
 @pytest.mark.parametrize("model,stencil,scheme", CASES)
-def test_jvp_matches_oracle(model, stencil, scheme):
+def test_jvp_matches_oracle(model, stencil, scheme, variant):
     po, pr, z0, v = setup(model, stencil, scheme, 97, 61, 17)
     z_ref, jv_ref = oracle.jvp(po, z0, v, 17)
     z_gpu, jv_gpu = gpu_jvp(pr, z0, v)
@@ -80,11 +88,14 @@ def test_jvp_band_height_invariance_and_linearity():
     po, pr, z0, v = setup("fk", "lap9", "rk4", 150, 90, 9)
     outs = []
     try:
-        for rows in (0, 2, 7, 90):
-            rd.set_tile_rows(rows)
-            outs.append(gpu_jvp(pr, z0, v)[1])
+        for var in ("sweep", "pipe"):
+            rd.set_kernel_variant(var)
+            for rows in (0, 2, 7, 90):
+                rd.set_tile_rows(rows)
+                outs.append(gpu_jvp(pr, z0, v)[1])
     finally:
         rd.set_tile_rows(0)
+        rd.set_kernel_variant(None)
     for o in outs[1:]:
         assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
     _, a = gpu_jvp(pr, z0, v)
