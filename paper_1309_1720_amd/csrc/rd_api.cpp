@@ -111,7 +111,8 @@ void derive_constants(const rd_problem* p, KConst& c) {
   c.nx = p->nx;
   c.ny = p->ny;
   c.sharp = std::isinf(p->step_k) ? 1 : 0;
-  c.k = c.sharp ? 0.0 : p->step_k;
+  c.k = p->step_k;
+  c.k6 = c.sharp ? 0.0 : 6.0 * p->step_k;
   c.dt = p->dt;
   c.h2 = p->dt * 0.5;
   c.h6 = p->dt / 6.0;

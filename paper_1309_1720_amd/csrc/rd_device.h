@@ -45,7 +45,8 @@ struct KConst {
   int nsx, nby, ty;  // launch geometry: column strips, row bands, rows per band
   int sharp;         // 1: Heaviside step instead of H_k
   int variant;       // fused-step kernel variant (StepVariant)
-  double k;          // H_k sharpness
+  double k;          // H_k sharpness (+inf for the Heaviside step)
+  double k6;         // dH_k/dt scale 6 k (0 for the Heaviside step)
   double dt, h2, h6; // dt, dt/2, dt/6
   double cD;         // D_par / dx^2 (isotropic stencils)
   double inv_dx2;    // 1 / dx^2 (anisotropic flux form)
@@ -61,27 +62,25 @@ template <> struct ModelTraits<RD_MODEL_BOCF> { static constexpr int NV = 4; };
 
 // ---------------------------------------------------------------------------
 // Smoothed step: t = kx + 1/2 clamped to [0, 1], H = t^2 (3 - 2t).  Clamping
-// reproduces the 0 and 1 branches exactly (0*0*3 = 0, 1*1*1 = 1).  Used only
-// by the gated models, so it may fuse multiply-adds.
+// reproduces the 0 and 1 branches exactly (0*0*3 = 0, 1*1*1 = 1).  The
+// Heaviside limit uses the same instructions with k = +inf: t is -inf or +inf
+// away from x = 0 and NaN at x = 0 (inf * 0), and the clamp max(min(t, 1), 0)
+// takes NaN to 1 (min returns its non-NaN operand), so H(0) = 1 -- no branch
+// and no select.  Used only by the gated models, so it may fuse multiply-adds.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double step_h(double x, const KConst& c) {
-  if (c.sharp) return x >= 0.0 ? 1.0 : 0.0;
   double t = fma(c.k, x, 0.5);
-  t = fmin(fmax(t, 0.0), 1.0);
+  t = fmax(fmin(t, 1.0), 0.0);
   return (t * t) * fma(-2.0, t, 3.0);
 }
 
-// H and dH/dx = 6 k t (1 - t) (zero outside the transition and for Heaviside).
+// H and dH/dx = 6 k t (1 - t), which is zero outside the transition and for
+// the Heaviside step (k6 = 0 there, and t (1 - t) = 0).
 __device__ __forceinline__ void step_h_d(double x, const KConst& c, double& h, double& dh) {
-  if (c.sharp) {
-    h = x >= 0.0 ? 1.0 : 0.0;
-    dh = 0.0;
-    return;
-  }
   double t = fma(c.k, x, 0.5);
-  t = fmin(fmax(t, 0.0), 1.0);
+  t = fmax(fmin(t, 1.0), 0.0);
   h = (t * t) * fma(-2.0, t, 3.0);
-  dh = ((6.0 * c.k) * t) * (1.0 - t);
+  dh = c.k6 * (t * (1.0 - t));
 }
 
 // ---------------------------------------------------------------------------
@@ -302,11 +301,24 @@ __device__ __forceinline__ void eval_rates(const KConst& c, const double* y, dou
 
 // ---------------------------------------------------------------------------
 // Cross-lane access.  Lane l holds column x0 + l; the previous/next lane holds
-// the west/east neighbour.  Lanes 0 and 63 read their own value (they are halo
-// lanes whose results never reach an output).
+// the west/east neighbour.  Lanes 0 and 63 are halo lanes whose results never
+// reach an output.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double from_west(double v) { return __shfl_up(v, 1, kWave); }
-__device__ __forceinline__ double from_east(double v) { return __shfl_down(v, 1, kWave); }
+// The moves are DPP whole-wavefront shifts by one lane (wave_shr:1 reads the
+// lane below, wave_shl:1 the lane above), executed by the vector ALU.  Lanes
+// 0 and 63, which have no source lane, read zero; they are halo lanes.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, true);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi2 << 32) | (unsigned int)lo2);
+}
+__device__ __forceinline__ double from_west(double v) { return dpp_shift<kDppWaveShr1>(v); }
+__device__ __forceinline__ double from_east(double v) { return dpp_shift<kDppWaveShl1>(v); }
 
 // Per-lane geometry of a column.
 struct Column {
@@ -351,7 +363,8 @@ __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool anis
 // (up = cen at rho = 0, dn = cen at rho = ny-1).  All lanes of the wave must
 // call it together (cross-lane reads).  EDGE: some lane of this wave holds
 // the first or last column of the grid, so x-mirrors must be applied.
-template <int STENCIL, bool EDGE>
+// YEDGE = false promises 0 < rho < ny - 1 (no boundary face in y).
+template <int STENCIL, bool EDGE, bool YEDGE = true>
 __device__ __forceinline__ double diffusion(double up, double cen, double dn, const Column& col,
                                             int rho, const KConst& c) {
   if constexpr (STENCIL == RD_LAP5) {
@@ -385,8 +398,8 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
     const double wDc = mw ? dn : wD, eDc = me ? dn : eD;
     double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (dn - cen);
     double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (cen - up);
-    if (rho == c.ny - 1) fys = 0.0;
-    if (rho == 0) fyn = 0.0;
+    if (YEDGE && rho == c.ny - 1) fys = 0.0;
+    if (YEDGE && rho == 0) fyn = 0.0;
     return ((fxe - fxw) + (fys - fyn)) * c.inv_dx2;
   }
 }

@@ -22,6 +22,8 @@
 // is bit-identical to the plain step.
 #pragma once
 
+#include <type_traits>
+
 #include "rd_device.h"
 
 namespace rd {
@@ -58,11 +60,14 @@ template <> struct Scheme<4> {
 };
 
 // Waves per SIMD each kernel's register budget is sized for (the largest
-// count that still needs no scratch spills).
+// count that still needs no scratch spills once the four stages of a steady
+// RK4 iteration are interleaved).
 template <int MODEL, int STENCIL, int NS, int MODE> struct SweepOccupancy {
-  static constexpr bool heavy = MODEL == RD_MODEL_BOCF || STENCIL == RD_LAP9_ANISO;
-  static constexpr int value =
-      MODE == kModeTangent ? (NS == 4 ? 1 : 2) : (NS == 4 && heavy ? 2 : 3);
+  static constexpr bool heavy = MODEL == RD_MODEL_BOCF && STENCIL == RD_LAP9_ANISO;
+  static constexpr int value = MODE == kModeTangent ? (NS == 4 || (NS == 2 && MODEL == RD_MODEL_BOCF) ? 1 : 2)
+                               : NS == 4            ? (heavy ? 1 : 2)
+                               : NS == 2 && heavy   ? 2
+                                                    : 3;
 };
 
 // One wavefront's share of a sweep: strip wid % nsx, band wid / nsx of the
@@ -129,7 +134,12 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
     for (int f = 0; f < NF; ++f) pre[f] = in[f][o];
   }
 
-  for (int r = r_first; r <= r_last; ++r) {
+  // One iteration: load row r, run stage s on row r - s.  STEADY marks
+  // iterations in which every stage is active, the rows involved are interior
+  // (no y-mirror), and the next row exists: its body is free of branches, so
+  // the independent reactions of the stages can be interleaved.
+  auto iter = [&](int r, auto steady_tag) __attribute__((always_inline)) {
+    constexpr bool STEADY = decltype(steady_tag)::value;
     // Advance the register rings by one row.
 #pragma unroll
     for (int k = ZR - 1; k > 0; --k)
@@ -150,10 +160,10 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
       for (int f = 0; f < NF; ++f)
         if (!diffusive(f)) yg[s][f] = ygn[s][f];
     }
-    if (r < load_end) {
+    if (STEADY || r < load_end) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) zr[0][f] = pre[f];
-      if (r + 1 < load_end) {
+      if (STEADY || r + 1 < load_end) {
         const size_t o = (size_t)(r + 1) * nx + cx;
 #pragma unroll
         for (int f = 0; f < NF; ++f) pre[f] = in[f][o];
@@ -164,9 +174,11 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
     for (int s = 1; s <= NS; ++s) {
       if (STAGES && s == NS) continue;  // k_NS is not a stage input
       const int rho = r - s;
-      const int lo = max(yA - (NS - s), 0);
-      const int hi = min(yB + (NS - s), c.ny);
-      if (rho < lo || rho >= hi) continue;  // wave-uniform
+      if (!STEADY) {
+        const int lo = max(yA - (NS - s), 0);
+        const int hi = min(yB + (NS - s), c.ny);
+        if (rho < lo || rho >= hi) continue;  // wave-uniform
+      }
 
       double y[NF], up[ND], dn[ND];
       if (s == 1) {
@@ -188,22 +200,27 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
           dn[d] = yu[s][0][d];
         }
       }
+      if (!STEADY) {
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        if (rho == 0) up[d] = y[comp(d)];
-        if (rho == c.ny - 1) dn[d] = y[comp(d)];
+        for (int d = 0; d < ND; ++d) {
+          if (rho == 0) up[d] = y[comp(d)];
+          if (rho == c.ny - 1) dn[d] = y[comp(d)];
+        }
       }
 
       double lap[ND];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) lap[d] = diffusion<STENCIL, EDGE>(up[d], y[comp(d)], dn[d], col, rho, c);
+      for (int d = 0; d < ND; ++d)
+        lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c);
       double k[NF];
       eval_rates<MODEL, TAN>(c, y, k);
 #pragma unroll
       for (int d = 0; d < ND; ++d) k[comp(d)] = lap[d] + k[comp(d)];
 
+      // the last stage's row lies inside the band in every steady iteration
+      const bool last_core = out_col && (STEADY || (rho >= yA && rho < yB));
       if (NS == 1) {
-        if (out_col && rho >= yA && rho < yB) {
+        if (!STAGES && last_core) {
           const size_t o = (size_t)rho * nx + gx;
 #pragma unroll
           for (int f = 0; f < NF; ++f) out[f][o] = zr[1][f] + c.dt * k[f];
@@ -230,13 +247,25 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 #pragma unroll
           for (int f = 1; f < NV; ++f) ys[s - 1][f][o] = ygn[s + 1][f];
         }
-      } else if (!STAGES && out_col && rho >= yA && rho < yB) {
+      } else if (!STAGES && last_core) {
         const double bw = NS == 4 ? c.h6 : c.h2;
         const size_t o = (size_t)rho * nx + gx;
 #pragma unroll
         for (int f = 0; f < NF; ++f) out[f][o] = zr[s][f] + bw * acc[s - 1][f];
       }
     }
+  };
+
+  // Steady iterations: r >= yA + NS (every stage's row is at or past its
+  // band start), r >= NS + 1 (no row 0), r + 1 < min(yB + NS, ny) (row r + 1
+  // is loaded; no row ny - 1 is processed).
+  const int ss_lo = max(yA + NS, NS + 1);
+  const int ss_hi = min(yB + NS - 1, c.ny - 1);
+  for (int r = r_first; r <= r_last; ++r) {
+    if (r >= ss_lo && r < ss_hi)
+      iter(r, std::true_type{});
+    else
+      iter(r, std::false_type{});
   }
 }
 

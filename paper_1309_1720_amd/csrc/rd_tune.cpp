@@ -19,7 +19,10 @@ namespace rd {
 
 namespace {
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, int, int>, Plan> g_cache;
+// Keyed by the problem and by the overrides in force: a fixed variant or band
+// height restricts the candidates, so it selects its own cache entry.
+using Key = std::tuple<int, int, int, int, int, int, int, int>;
+std::map<Key, Plan> g_cache;
 bool g_enabled = true;
 int g_override = -1;          // rows per band (> 0: fixed)
 int g_variant_override = -1;  // kernel variant (>= 0: fixed)
@@ -70,13 +73,14 @@ static Plan apply_overrides(Plan p, int ny) {
 
 Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
                 const std::function<hipError_t(Plan)>& trial, bool allow_pipe) {
-  const auto key = std::make_tuple(kind, model, stencil, scheme, nx, ny);
   bool tune;
   Plan fallback;
   std::vector<Plan> cands;
+  Key key;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     const int vfix = allow_pipe ? g_variant_override : kVariantSweep;
+    key = Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0);
     fallback = apply_overrides(heuristic_plan(nx, ny, ns, vfix), ny);
     if (!allow_pipe) fallback.variant = kVariantSweep;
     if (g_override > 0 && vfix >= 0) return fallback;  // fully fixed
@@ -84,7 +88,7 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
     if (it != g_cache.end()) return it->second;
     tune = g_enabled;
     if (vfix != kVariantPipe)
-      for (int ty : {2, 3, 4, 6, 8, 10, 12, 16, 24})
+      for (int ty : {2, 3, 4, 6, 8, 10, 12, 16, 24, 32, 48, 64})
         if (ty <= ny && ty >= ns && (g_override <= 0 || ty == fallback.ty)) cands.push_back(Plan{kVariantSweep, ty});
     if (allow_pipe && vfix != kVariantSweep)
       for (int ty : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96})
@@ -132,9 +136,10 @@ int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int
 
 Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_cache.find(std::make_tuple(kind, model, stencil, scheme, nx, ny));
+  const int vfix = allow_pipe ? g_variant_override : kVariantSweep;
+  auto it = g_cache.find(Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0));
   if (it != g_cache.end()) return it->second;
-  Plan p = apply_overrides(heuristic_plan(nx, ny, ns, allow_pipe ? g_variant_override : kVariantSweep), ny);
+  Plan p = apply_overrides(heuristic_plan(nx, ny, ns, vfix), ny);
   if (!allow_pipe) p.variant = kVariantSweep;
   return p;
 }

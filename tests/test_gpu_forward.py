@@ -122,6 +122,34 @@ def test_degenerate_and_ragged_grids(nx, ny, model, stencil, scheme, variant):
     assert rel_linf(gpu_step(pr, z0), oracle.step(po, z0, 5)) <= TOL
 
 
+THRESHOLDS = {"fk": ("u_c", "u_v"), "bocf": ("u_o", "theta_v", "theta_w", "theta_v_minus", "theta_o")}
+
+
+def on_thresholds(model, z0):
+    """Put every threshold of the model's gates exactly into some cells of u,
+    where the Heaviside step must give H(0) = 1."""
+    vals = dict(zip(ri.PARAM_NAMES[model], ri.params_array(model)))
+    for k, name in enumerate(THRESHOLDS[model]):
+        z0[0][k::7, ::5] = vals[name]
+    return z0
+
+
+@pytest.mark.parametrize("variant", ["sweep", "pipe"], indirect=True)
+@pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rk4"), ("bocf", "lap5", "heun"),
+                                                  ("bocf", "lap9_aniso", "euler")])
+def test_heaviside_limit_matches_oracle(model, stencil, scheme, variant):
+    """step_k = inf selects the Heaviside step with H(0) = 1."""
+    w = workload(model, stencil, scheme, 97, 70, step_k=math.inf)
+    po, pr = problems(w, nsteps=3)
+    z0 = on_thresholds(model, ri.random_fields(model, 97, 70, 23))
+    ref = oracle.step(po, z0, 3)
+    got = gpu_step(pr, z0)
+    assert rel_linf(got, ref) <= TOL
+    # one Euler step is a single evaluation: a wrong H(0) shows on the planted cells
+    po1, pr1 = problems(dict(w, scheme="euler"), nsteps=1)
+    assert rel_linf(gpu_step(pr1, z0), oracle.step(po1, z0, 1)) <= TOL
+
+
 @pytest.mark.parametrize("steps", [0, 1, 2, 7])
 def test_step_counts_and_checkpoints(steps):
     w = workload("fk", "lap9", "rk4", 70, 45)

@@ -53,6 +53,21 @@ def test_jvp_matches_oracle(model, stencil, scheme, variant):
     assert all(np.array_equal(a, b) for a, b in zip(z_gpu, z_fwd))
 
 
+@pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rk4"), ("bocf", "lap5", "heun")])
+def test_jvp_heaviside_limit(model, stencil, scheme):
+    """step_k = inf: the gates are piecewise constant, so their derivative
+    terms vanish and the tangent follows the remaining terms."""
+    w = ri.workload(BASE[model], model=model, stencil=stencil, scheme=scheme, nx=90, ny=66,
+                    step_k=float("inf"))
+    po, pr = problems(w, nsteps=9)
+    z0 = ri.random_fields(model, 90, 66, 8)
+    v = ri.direction(len(z0), 90, 66, 108)
+    z_ref, jv_ref = oracle.jvp(po, z0, v, 9)
+    z_gpu, jv_gpu = gpu_jvp(pr, z0, v)
+    assert rel_linf(z_gpu, z_ref) <= TOL
+    assert rel_linf(jv_gpu, jv_ref) <= TOL
+
+
 @pytest.mark.parametrize("model,stencil,n,steps", [("fk", "lap9", 128, 200), ("barkley", "lap5", 130, 300),
                                                    ("bocf", "lap9_aniso", 96, 150)])
 def test_jvp_long_horizon(model, stencil, n, steps):
