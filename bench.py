@@ -116,14 +116,18 @@ def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
             "timed_steps": steps}
 
 
-def _timed(torch, stream, fn):
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    fn()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3
+def _timed(torch, stream, fn, reps=1):
+    """Device time of fn() between two events on `stream` (best of `reps`)."""
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    return best
 
 
 def other_workloads(rd, torch, dev):
@@ -171,13 +175,13 @@ def other_workloads(rd, torch, dev):
     for q in probs:
         q.nsteps = n
     cells = sum(x["nx"] * x["ny"] for x in ws)
-    sec_b = _timed(torch, stream, lambda: rd.step_batched(probs, fields, tans))
-    sec_f = _timed(torch, stream, lambda: rd.step_batched(probs, fields, None))
+    sec_b = _timed(torch, stream, lambda: rd.step_batched(probs, fields, tans), reps=3)
+    sec_f = _timed(torch, stream, lambda: rd.step_batched(probs, fields, None), reps=3)
 
     def per_instance():
         for q, f, t in zip(probs, fields, tans):
             rd.jvp(q, f, t)
-    sec_s = _timed(torch, stream, per_instance)
+    sec_s = _timed(torch, stream, per_instance, reps=3)
     out["fk_ensemble_64_jvp"] = {"steps": n, "cells": cells, "rate_jvp": cells * n / sec_b,
                                  "rate_forward": cells * n / sec_f, "jvp_over_forward": sec_b / sec_f,
                                  "per_instance_calls_over_batched": sec_s / sec_b,

@@ -158,11 +158,27 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+# One workspace buffer per (device, stream), grown on demand and reused by
+# later calls on that stream (stream order keeps consecutive calls apart).
+_WORKSPACES: dict = {}
+
+
 def _workspace(nbytes: int, device):
     if nbytes == 0:
         return None, 0
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    dev = torch.device(device)
+    key = (dev.index if dev.index is not None else torch.cuda.current_device(), _stream(dev))
+    ws = _WORKSPACES.get(key)
+    if ws is None or ws.numel() < nbytes:
+        _WORKSPACES.pop(key, None)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _WORKSPACES[key] = ws
     return ws, ws.data_ptr()
+
+
+def release_workspaces() -> None:
+    """Drop the cached workspace buffers (returned to torch's allocator)."""
+    _WORKSPACES.clear()
 
 
 def n_fields(model: str) -> int:

@@ -93,7 +93,7 @@ extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* 
   BatchInst* table = (BatchInst*)ws;
   std::vector<BatchInst> inst(nbatch);
   char* next = (char*)ws + table_bytes(nbatch);
-  int max_ny = 1;
+  int max_nx = 1, max_ny = 1;
   uint32_t shape_hash = 2166136261u;
   for (int32_t i = 0; i < nbatch; ++i) {
     BatchInst& I = inst[i];
@@ -105,6 +105,7 @@ extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* 
       I.b[f] = (double*)next;
       next += field_bytes(&probs[i]);
     }
+    max_nx = std::max(max_nx, I.nx);
     max_ny = std::max(max_ny, I.ny);
     shape_hash = (shape_hash ^ (uint32_t)I.nx) * 16777619u;
     shape_hash = (shape_hash ^ (uint32_t)I.ny) * 16777619u;
@@ -151,8 +152,26 @@ extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* 
     args.parity = 0;  // reads the caller's arrays, writes workspace only
     return launch_batch_kernel(tangent, q.model, q.stencil, q.scheme, args, s);
   };
-  const int ty = tuned_rows(kTuneBatched + (tangent ? 8 : 0), q.model, q.stencil, q.scheme,
-                            (int)(shape_hash & 0x7fffffff), max_ny, ns, s, trial);
+  // Untuned start: the tallest bands that still give every SIMD a few waves.
+  auto total_waves = [&](int ty) {
+    long long w = 0;
+    for (auto& I : inst) {
+      KConst g;
+      g.nx = I.nx;
+      g.ny = I.ny;
+      set_geometry(g, ns, ty);
+      w += (long long)g.nsx * g.nby;
+    }
+    return w;
+  };
+  int start_ty = 4;
+  for (int ty : {64, 48, 32, 24, 16, 12, 8, 6})
+    if (total_waves(ty) >= 4096) {
+      start_ty = ty;
+      break;
+    }
+  const int ty = tuned_rows(kTuneBatched + (tangent ? 8 : 0), q.model, q.stencil, q.scheme, max_nx, max_ny,
+                            ns, s, trial, (int)(shape_hash & 0x7fffffff), start_ty);
   hipError_t e = plan(ty);
   if (e != hipSuccess) return hip_fail(e, "batch table setup");
 

@@ -25,15 +25,19 @@ struct Plan {
   int ty;       // rows per band
 };
 // Tunes kernel variant and band height together (trial launches write only
-// workspace); allow_pipe = false restricts to the sweep kernel.
+// workspace); allow_pipe = false restricts to the sweep kernel.  shape_key
+// distinguishes launches whose grids nx x ny do not describe (batches);
+// fallback_ty > 0 replaces the single-grid heuristic's band height.
 Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
-                const std::function<hipError_t(Plan)>& trial, bool allow_pipe);
+                const std::function<hipError_t(Plan)>& trial, bool allow_pipe, int shape_key = 0,
+                int fallback_ty = 0);
 Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe);
 int heuristic_rows(int nx, int ny, int ns);
 // Override, else cached tuning result, else heuristic (never tunes).
 int current_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns);
 int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns,
-               hipStream_t s, const std::function<hipError_t(int)>& trial);
+               hipStream_t s, const std::function<hipError_t(int)>& trial, int shape_key = 0,
+               int fallback_ty = 0);
 size_t align_up(size_t x, size_t a);
 size_t field_bytes(const rd_problem* p);
 int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hipStream_t s);

@@ -70,6 +70,22 @@ template <int MODEL, int STENCIL, int NS, int MODE> struct SweepOccupancy {
                                                     : 3;
 };
 
+// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{}).
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, I + 1>(f);
+  }
+}
+
+// Rows of the state loaded ahead of use (deeper where the per-row arithmetic
+// is short and registers are plentiful).
+template <int MODEL, int NS, int MODE> struct SweepPrefetch {
+  static constexpr int NF = (MODE == kModeTangent ? 2 : 1) * ModelTraits<MODEL>::NV;
+  static constexpr int value = NF <= 2 ? 4 : MODE == kModeTangent ? 1 : 2;
+};
+
 // One wavefront's share of a sweep: strip wid % nsx, band wid / nsx of the
 // grid described by c, reading `in` and writing `out` (or the stage inputs
 // `ys`).  Shared by the single-grid and the batched kernels.
@@ -123,23 +139,34 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
     for (int f = 0; f < NF; ++f) yg[s][f] = ygn[s][f] = 0.0;
   }
 
-  // Rows are prefetched one iteration ahead so that a whole iteration of
-  // arithmetic covers the load latency.
-  double pre[NF];
+  // Rows are prefetched PF iterations ahead, so that PF iterations of
+  // arithmetic cover the load latency: pre[p] holds row r + p when iteration
+  // r starts.  Loads past the band's last input row re-read that row (in
+  // bounds, never used), which keeps the steady iterations free of branches.
+  constexpr int PF = SweepPrefetch<MODEL, NS, MODE>::value;
+  double pre[PF][NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) pre[f] = 0.0;
-  if (r_first < load_end) {
-    const size_t o = (size_t)r_first * nx + cx;
+  for (int p = 0; p < PF; ++p) {
+    const int row = min(r_first + p, load_end - 1);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) pre[f] = in[f][o];
+    for (int f = 0; f < NF; ++f) pre[p][f] = 0.0;
+    if (row >= 0) {
+      const size_t o = (size_t)row * nx + cx;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) pre[p][f] = in[f][o];
+    }
   }
 
-  // One iteration: load row r, run stage s on row r - s.  STEADY marks
-  // iterations in which every stage is active, the rows involved are interior
-  // (no y-mirror), and the next row exists: its body is free of branches, so
-  // the independent reactions of the stages can be interleaved.
-  auto iter = [&](int r, auto steady_tag) __attribute__((always_inline)) {
+  // One iteration: take row r, run stage s on row r - s.  STEADY marks
+  // iterations in which every stage is active and the rows involved are
+  // interior (no y-mirror): its body is free of branches, so the independent
+  // reactions of the stages can be interleaved.  SLOT < 0: the prefetch ring
+  // shifts by one row (pre[0] is row r); SLOT = q: the loop is unrolled by PF
+  // and slot q holds row r, so no prefetched register is read before its
+  // turn (a shift would wait for the youngest load).
+  auto iter = [&](int r, auto steady_tag, auto slot_tag) __attribute__((always_inline)) {
     constexpr bool STEADY = decltype(steady_tag)::value;
+    constexpr int SLOT = decltype(slot_tag)::value;
     // Advance the register rings by one row.
 #pragma unroll
     for (int k = ZR - 1; k > 0; --k)
@@ -161,13 +188,18 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         if (!diffusive(f)) yg[s][f] = ygn[s][f];
     }
     if (STEADY || r < load_end) {
+      constexpr int q = SLOT < 0 ? 0 : SLOT;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) zr[0][f] = pre[f];
-      if (STEADY || r + 1 < load_end) {
-        const size_t o = (size_t)(r + 1) * nx + cx;
+      for (int f = 0; f < NF; ++f) zr[0][f] = pre[q][f];
+      if constexpr (SLOT < 0) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) pre[f] = in[f][o];
+        for (int p = 0; p + 1 < PF; ++p)
+#pragma unroll
+          for (int f = 0; f < NF; ++f) pre[p][f] = pre[p + 1][f];
       }
+      const size_t o = (size_t)min(r + PF, load_end - 1) * nx + cx;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) pre[SLOT < 0 ? PF - 1 : q][f] = in[f][o];
     }
 
 #pragma unroll
@@ -257,15 +289,25 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   };
 
   // Steady iterations: r >= yA + NS (every stage's row is at or past its
-  // band start), r >= NS + 1 (no row 0), r + 1 < min(yB + NS, ny) (row r + 1
-  // is loaded; no row ny - 1 is processed).
-  const int ss_lo = max(yA + NS, NS + 1);
-  const int ss_hi = min(yB + NS - 1, c.ny - 1);
-  for (int r = r_first; r <= r_last; ++r) {
-    if (r >= ss_lo && r < ss_hi)
-      iter(r, std::true_type{});
+  // band start), r >= NS + 1 (no stage on row 0), r < min(yB + NS, ny) (row r
+  // is an input row, so no stage runs on row ny - 1 or past its band end).
+  // Ramp-up and ramp-down iterations shift the prefetch ring; the steady run
+  // between them goes PF rows at a time with fixed slots (its rows r + q sit
+  // in slot q because the ring is in order when the run starts and ends).
+  using Shift = std::integral_constant<int, -1>;
+  const int ss_lo = min(max(yA + NS, NS + 1), r_last + 1);
+  const int ss_hi = max(load_end, ss_lo);
+  const int ss_end = ss_lo + (ss_hi - ss_lo) / PF * PF;
+  int r = r_first;
+  for (; r < ss_lo; ++r) iter(r, std::false_type{}, Shift{});
+  for (; r < ss_end; r += PF) {
+    static_for<PF>([&](auto q) { iter(r + q, std::true_type{}, q); });
+  }
+  for (; r <= r_last; ++r) {
+    if (r < ss_hi)
+      iter(r, std::true_type{}, Shift{});
     else
-      iter(r, std::false_type{});
+      iter(r, std::false_type{}, Shift{});
   }
 }
 

@@ -21,7 +21,7 @@ namespace {
 std::mutex g_mu;
 // Keyed by the problem and by the overrides in force: a fixed variant or band
 // height restricts the candidates, so it selects its own cache entry.
-using Key = std::tuple<int, int, int, int, int, int, int, int>;
+using Key = std::tuple<int, int, int, int, int, int, int, int, int>;
 std::map<Key, Plan> g_cache;
 bool g_enabled = true;
 int g_override = -1;          // rows per band (> 0: fixed)
@@ -72,7 +72,8 @@ static Plan apply_overrides(Plan p, int ny) {
 }
 
 Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
-                const std::function<hipError_t(Plan)>& trial, bool allow_pipe) {
+                const std::function<hipError_t(Plan)>& trial, bool allow_pipe, int shape_key,
+                int fallback_ty) {
   bool tune;
   Plan fallback;
   std::vector<Plan> cands;
@@ -80,8 +81,10 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
   {
     std::lock_guard<std::mutex> lk(g_mu);
     const int vfix = allow_pipe ? g_variant_override : kVariantSweep;
-    key = Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0);
-    fallback = apply_overrides(heuristic_plan(nx, ny, ns, vfix), ny);
+    key = Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0, shape_key);
+    Plan start = heuristic_plan(nx, ny, ns, vfix);
+    if (fallback_ty > 0) start.ty = fallback_ty < ny ? fallback_ty : ny;
+    fallback = apply_overrides(start, ny);
     if (!allow_pipe) fallback.variant = kVariantSweep;
     if (g_override > 0 && vfix >= 0) return fallback;  // fully fixed
     auto it = g_cache.find(key);
@@ -129,15 +132,15 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
 }
 
 int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
-               const std::function<hipError_t(int)>& trial) {
+               const std::function<hipError_t(int)>& trial, int shape_key, int fallback_ty) {
   return tuned_plan(kind, model, stencil, scheme, nx, ny, ns, s,
-                    [&](Plan p) { return trial(p.ty); }, false).ty;
+                    [&](Plan p) { return trial(p.ty); }, false, shape_key, fallback_ty).ty;
 }
 
 Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int vfix = allow_pipe ? g_variant_override : kVariantSweep;
-  auto it = g_cache.find(Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0));
+  auto it = g_cache.find(Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0, 0));
   if (it != g_cache.end()) return it->second;
   Plan p = apply_overrides(heuristic_plan(nx, ny, ns, vfix), ny);
   if (!allow_pipe) p.variant = kVariantSweep;
