@@ -1,0 +1,136 @@
+"""Condense rocprofv3 output of the benchmark's fused step into the summaries
+under profiles/ (text only) and the traffic record bench.py reads.
+
+Runs of rocprofv3 (each its own process, from /tmp, band height pinned):
+
+    rocprofv3 --kernel-trace --stats --output-format csv -d OUT/stats -o fk -- \\
+        python3 REPO/bench.py --steps 4000 --warmup 50 --no-cpu-baseline --no-jvp \\
+        --no-other-workloads --variant sweep --tile-rows T
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o fk -- \\
+        python3 REPO/bench.py --steps 20 --warmup 2 --no-cpu-baseline --no-jvp \\
+        --no-other-workloads --variant sweep --tile-rows T --calibration-copy
+    (the same with --pmc WRITE_SIZE into OUT/write, and with the SQ counters
+    below into OUT/sq)
+
+then:  python bench_profile.py OUT T
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import json
+import os
+import sys
+
+import bench
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PROFILES = os.path.join(HERE, "profiles")
+KERNEL = "rd::sweep_kernel<2, 9, 4, 0>"
+CALIB = "CUDAFunctorOnSelf_add<double>"
+CALIB_BYTES = 1 << 29  # 2^26 doubles read and the same written
+SQ_COUNTERS = ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+               "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "SQ_INSTS_SALU"]
+BENCH_ARGS = "--no-cpu-baseline --no-jvp --no-other-workloads --variant sweep"
+
+
+def _rows(root: str, pattern: str) -> list[dict]:
+    out = []
+    for f in sorted(glob.glob(os.path.join(root, "**", pattern), recursive=True)):
+        with open(f) as fh:
+            out += list(csv.DictReader(fh))
+    return out
+
+
+def _counters(root: str) -> dict:
+    """(kernel, counter) -> mean value per dispatch."""
+    agg = collections.defaultdict(list)
+    for r in _rows(root, "*counter_collection.csv"):
+        agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def _pick(counters: dict, needle: str, counter: str) -> float:
+    vals = [v for (k, c), v in counters.items() if needle in k and c == counter]
+    if len(vals) != 1:
+        raise RuntimeError(f"expected one kernel matching {needle!r} with {counter}, found {len(vals)}")
+    return vals[0]
+
+
+def main(out: str, tile_rows: int) -> None:
+    cells = 1024 * 1024
+    alg = 2 * 3 * 8 * cells
+    cmd = lambda extra, steps: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o fk -- "
+                                f"python3 <repo>/bench.py --steps {steps} --warmup {2 if steps == 20 else 50} "
+                                f"{BENCH_ARGS} --tile-rows {tile_rows}")
+
+    # kernel timings
+    stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
+    lines = ["# Fused RK4 step, Fenton-Karma 1024x1024 (9-point, FP64) — kernel timings", "",
+             "Command:", "", "    " + cmd("--kernel-trace --stats", 4000), "",
+             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:6]:
+        name = r["Name"].split("(")[0]
+        lines.append(f"| `{name[:80]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['Percentage']):.1f} |")
+    main_row = [r for r in stats if r["Name"].startswith("void " + KERNEL)]
+    if main_row:
+        avg = float(main_row[0]["AverageNs"]) / 1e3
+        lines += ["", f"The calls are the warm-up and timed steps, one launch per step; the fused step "
+                      f"averages {avg:.2f} us = {cells / (avg * 1e-6):.3e} cell-updates/s, "
+                      f"{alg / (avg * 1e-6) / 1e9:.0f} GB/s algorithmic."]
+    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    # traffic
+    fetch = _counters(os.path.join(out, "fetch"))
+    write = _counters(os.path.join(out, "write"))
+    f_k, w_k = _pick(fetch, KERNEL, "FETCH_SIZE"), _pick(write, KERNEL, "WRITE_SIZE")
+    f_c, w_c = _pick(fetch, CALIB, "FETCH_SIZE"), _pick(write, CALIB, "WRITE_SIZE")
+    fs, wsc = CALIB_BYTES / 1024 / f_c, CALIB_BYTES / 1024 / w_c
+    hbm = (f_k * fs + w_k * wsc) * 1024
+    rec = {"kernel": KERNEL + " (Fenton-Karma, 9-point, RK4, state)",
+           "workload": "fenton_karma_1024x1024_lap9_rk4", "cells": cells,
+           "kernel_sha": bench.kernel_hash(), "tile_rows": tile_rows,
+           "fetch_kib_per_dispatch": round(f_k, 1), "write_kib_per_dispatch": round(w_k, 1),
+           "calibration": {"kernel": "torch.add(src, 0.0, out=dst), 2^26 doubles",
+                           "bytes_read": CALIB_BYTES, "bytes_written": CALIB_BYTES,
+                           "fetch_kib": round(f_c, 1), "write_kib": round(w_c, 1),
+                           "fetch_scale": fs, "write_scale": wsc},
+           "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg}
+    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+
+    sq = _counters(os.path.join(out, "sq"))
+    g = {c: _pick(sq, KERNEL, c) for c in SQ_COUNTERS}
+    waves = g["SQ_WAVES"]
+    lines = ["# Fused RK4 step, Fenton-Karma 1024x1024 — hardware counters", "",
+             "Commands (each a run of its own):", "",
+             "    " + cmd("--pmc FETCH_SIZE", 20) + " --calibration-copy",
+             "    " + cmd("--pmc WRITE_SIZE", 20) + " --calibration-copy",
+             "    " + cmd("--pmc " + " ".join(SQ_COUNTERS), 20),
+             "    python3 <repo>/bench_profile.py <out> " + str(tile_rows), "",
+             "## Memory traffic (KiB per dispatch)", "",
+             "| kernel | FETCH_SIZE | WRITE_SIZE |", "|---|---|---|",
+             f"| `{KERNEL}` | {f_k:.1f} | {w_k:.1f} |",
+             f"| calibration copy, 2^26 doubles (512 MiB in, 512 MiB out) | {f_c:.0f} | {w_c:.0f} |", "",
+             f"Calibration: FETCH_SIZE is scaled by {fs:.3f} and WRITE_SIZE by {wsc:.3f}. Scaled traffic per "
+             f"launch: {f_k * fs:.0f} KiB read + {w_k * wsc:.0f} KiB written = {hbm / 1e6:.1f} MB, against "
+             f"{alg / 1e6:.1f} MB algorithmic (read and write the 3-field state once).", "",
+             "## Instruction and occupancy counters (per dispatch)", "",
+             "| counter | value | per wave |", "|---|---|---|"]
+    for c in SQ_COUNTERS:
+        lines.append(f"| {c} | {g[c]:.4g} | {g[c] / waves:.4g} |")
+    lines += ["", f"Lane-instructions per cell-update: {g['SQ_INSTS_VALU'] * 64 / cells:.0f}. Share of wave "
+                  f"time issuing VALU: {g['SQ_ACTIVE_INST_VALU'] / g['SQ_WAVE_CYCLES']:.2f}; waiting on "
+                  f"dependencies (memory): {g['SQ_WAIT_INST_ANY'] / g['SQ_WAVE_CYCLES']:.2f}."]
+    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(json.dumps(rec, indent=1))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], int(sys.argv[2]))

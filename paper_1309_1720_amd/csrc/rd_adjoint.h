@@ -76,10 +76,11 @@ void adjoint_kernel(AdjArgs a) {
   const KConst& c = a.c;
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+  const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
+  const int wid = __builtin_amdgcn_readfirstlane(blk * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (wid >= c.nsx * c.nby) return;  // whole waves only: no barrier follows
-  const int sx = wid % c.nsx;
-  const int by = wid / c.nsx;
+  const int sx = wid / c.nby;  // bands of one strip are consecutive
+  const int by = wid % c.nby;
   const int gx = sx * TX - NS + lane;
   const int cx = min(max(gx, 0), c.nx - 1);
   const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;

@@ -54,7 +54,8 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
 void batch_sweep_kernel(BatchArgs a) {
   constexpr int NF = (MODE == kModeTangent ? 2 : 1) * ModelTraits<MODEL>::NV;
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+  const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
+  const int wid = __builtin_amdgcn_readfirstlane(blk * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (wid >= a.total_waves) return;  // whole waves only: no barrier follows
   int lo = 0, hi = a.ninst - 1;
   while (lo < hi) {

@@ -335,6 +335,18 @@ __device__ __forceinline__ bool strip_touches_edge(int x0, const KConst& c) {
   return x0 <= 0 || x0 + kWave - 1 >= c.nx - 1;
 }
 
+// Launch order -> work order.  Workgroups are handed to the eight XCDs
+// round-robin (workgroup b runs on XCD b mod 8), and each XCD has its own L2.
+// This bijection of [0, nblocks) numbers the workgroups of one XCD
+// consecutively, so that work items with adjacent numbers -- vertically
+// adjacent bands of one strip, which share halo rows -- meet in the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_order(int b, int nblocks) {
+  const int q = nblocks / kXcds, rem = nblocks % kXcds;
+  const int x = b % kXcds;
+  return x * q + min(x, rem) + b / kXcds;
+}
+
 __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool aniso) {
   Column col;
   col.gx = gx;

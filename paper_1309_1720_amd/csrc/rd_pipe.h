@@ -60,8 +60,8 @@ __device__ __forceinline__ void pipe_block_impl(const double* const* in, double*
 
   const int lane = threadIdx.x & (kWave - 1);
   const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) + 1;  // this wave's stage
-  const int sx = blk % c.nsx;
-  const int by = blk / c.nsx;
+  const int sx = blk / c.nby;  // bands of one strip are consecutive
+  const int by = blk % c.nby;
   const int gx = sx * TX - NS + lane;
   const int cx = min(max(gx, 0), c.nx - 1);
   const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;
@@ -206,7 +206,7 @@ template <int MODEL, int STENCIL, int NS, int MODE>
 __device__ __forceinline__ void pipe_block(const double* const* in, double* const* out,
                                            double* const (*ys)[kMaxFields], const KConst& c, int blk,
                                            double* lds) {
-  const int x0 = (blk % c.nsx) * (kWave - 2 * NS) - NS;
+  const int x0 = (blk / c.nby) * (kWave - 2 * NS) - NS;
   if (strip_touches_edge(x0, c))
     pipe_block_impl<MODEL, STENCIL, NS, MODE, true>(in, out, ys, c, blk, lds);
   else
@@ -216,7 +216,7 @@ __device__ __forceinline__ void pipe_block(const double* const* in, double* cons
 template <int MODEL, int STENCIL, int NS, int MODE>
 __global__ __launch_bounds__(kWave * NS) void pipe_kernel(SweepArgs a) {
   __shared__ double lds[PipeShape<MODEL, NS, MODE>::total];
-  pipe_block<MODEL, STENCIL, NS, MODE>(a.in, a.out, a.ys, a.c, (int)blockIdx.x, lds);
+  pipe_block<MODEL, STENCIL, NS, MODE>(a.in, a.out, a.ys, a.c, xcd_order((int)blockIdx.x, (int)gridDim.x), lds);
 }
 
 template <int MODEL, int STENCIL, int NS, int MODE>

@@ -86,7 +86,7 @@ template <int MODEL, int NS, int MODE> struct SweepPrefetch {
   static constexpr int value = NF <= 2 ? 4 : MODE == kModeTangent ? 1 : 2;
 };
 
-// One wavefront's share of a sweep: strip wid % nsx, band wid / nsx of the
+// One wavefront's share of a sweep: strip wid / nby, band wid % nby of the
 // grid described by c, reading `in` and writing `out` (or the stage inputs
 // `ys`).  Shared by the single-grid and the batched kernels.
 template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE>
@@ -104,8 +104,8 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   auto diffusive = [](int f) { return f == 0 || (TAN && f == NV); };
 
   const int lane = threadIdx.x & (kWave - 1);
-  const int sx = wid % c.nsx;
-  const int by = wid / c.nsx;
+  const int sx = wid / c.nby;  // bands of one strip are consecutive
+  const int by = wid % c.nby;
   const int gx = sx * TX - NS + lane;
   const int cx = min(max(gx, 0), c.nx - 1);
   const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;
@@ -316,7 +316,7 @@ template <int MODEL, int STENCIL, int NS, int MODE>
 __device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
                                            double* const (*ys)[kMaxFields], const KConst& c,
                                            int wid) {
-  const int x0 = (wid % c.nsx) * (kWave - 2 * NS) - NS;
+  const int x0 = (wid / c.nby) * (kWave - 2 * NS) - NS;
   if (strip_touches_edge(x0, c))
     sweep_wave_impl<MODEL, STENCIL, NS, MODE, true>(in, out, ys, c, wid);
   else
@@ -327,7 +327,8 @@ template <int MODEL, int STENCIL, int NS, int MODE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
 void sweep_kernel(SweepArgs a) {
-  const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+  const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
+  const int wid = __builtin_amdgcn_readfirstlane(blk * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (wid >= a.c.nsx * a.c.nby) return;  // whole waves only: no barrier follows
   sweep_wave<MODEL, STENCIL, NS, MODE>(a.in, a.out, a.ys, a.c, wid);
 }
