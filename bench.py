@@ -144,6 +144,7 @@ def other_workloads(rd, torch, dev):
     p.nsteps = w["nsteps"]
     sec = _timed(torch, stream, lambda: rd.step(p, z))
     out["barkley_128_euler_1000"] = {"seconds": sec, "rate": 128 * 128 * w["nsteps"] / sec,
+                                     "steps_per_launch": rd.get_steps_per_launch(p),
                                      "us_per_step": sec / w["nsteps"] * 1e6,
                                      "hbm_frac": 32 * 128 * 128 * w["nsteps"] / sec / HBM_PEAK}
 
@@ -192,13 +193,15 @@ def other_workloads(rd, torch, dev):
     p = rd.Problem.from_workload(w, ri.params_array("barkley"))
     z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
     ck = torch.empty(rd.checkpoint_count(p) * 2 * w["nx"] * w["ny"], dtype=torch.float64, device=dev)
+    warm = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=2)
+    rd.step(warm, [t.clone() for t in z])   # tunes the forward plan outside the timed region
     sec_fwd = _timed(torch, stream, lambda: rd.step(p, z, ck))
     lam = [(2.0 * w["dx"] ** 2) * z[0].clone(), torch.zeros_like(z[1])]
     sec_vjp = _timed(torch, stream, lambda: rd.vjp(p, ck, lam))
     cells = w["nx"] * w["ny"]
     out["barkley_1024_rk4_adjoint_4000"] = {
         "forward_seconds": sec_fwd, "vjp_seconds": sec_vjp, "vjp_over_forward": sec_vjp / sec_fwd,
-        "forward_rate": cells * w["nsteps"] / sec_fwd,
+        "forward_rate": cells * w["nsteps"] / sec_fwd, "forward_steps_per_launch": rd.get_steps_per_launch(p),
         "forward_hbm_frac": 32 * cells * w["nsteps"] / sec_fwd / HBM_PEAK}
     return out
 

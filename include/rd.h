@@ -197,6 +197,17 @@ int rd_set_kernel_variant(int32_t variant);
  * heuristic starting plan). */
 int rd_get_plan(const rd_problem* p, int32_t op, int32_t* variant, int32_t* rows);
 
+/* Steps one launch of rd_step advances (temporal blocking, Sect. 4's kernel
+ * fusion carried across steps): 1, 2, 4 or 8.  Only the models with cheap
+ * reactions (diffusion, Barkley) chain steps, up to 8 stages per launch
+ * (Euler 8 steps, Heun 4, RK4 2); launches never pass a checkpoint.
+ * rd_set_steps_per_launch fixes it for later calls (capped by the model's
+ * maximum; <= 0: chosen by the autotuner, the default); other values return
+ * RD_EINVAL.  A performance knob: results do not depend on it.
+ * rd_get_steps_per_launch reports the value rd_step uses for `p`. */
+int rd_set_steps_per_launch(int32_t steps);
+int rd_get_steps_per_launch(const rd_problem* p, int32_t* steps);
+
 /* Band height the library uses for `op` (RD_OP_STEP, RD_OP_JVP, RD_OP_VJP) on
  * problem `p`: the override, else the autotuner's cached choice, else its
  * heuristic starting value. */

@@ -75,6 +75,8 @@ def lib() -> C.CDLL:
             "rd_get_tile_rows": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rd_set_kernel_variant": ([C.c_int32], C.c_int),
             "rd_get_plan": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+            "rd_set_steps_per_launch": ([C.c_int32], C.c_int),
+            "rd_get_steps_per_launch": ([P, C.POINTER(C.c_int32)], C.c_int),
             "rd_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -230,6 +232,20 @@ def get_plan(prob: Problem, op: str = "step"):
     v, r = C.c_int32(0), C.c_int32(0)
     _check(lib().rd_get_plan(C.byref(cp), OPS[op], C.byref(v), C.byref(r)))
     return {0: "sweep", 1: "pipe"}[v.value], r.value
+
+
+def set_steps_per_launch(steps) -> None:
+    """Fix the steps one rd_step launch advances (1, 2, 4, 8; capped by the
+    model's maximum) or None for the autotuner."""
+    _check(lib().rd_set_steps_per_launch(-1 if steps is None else int(steps)))
+
+
+def get_steps_per_launch(prob: Problem) -> int:
+    """Steps per launch rd_step uses for ``prob``."""
+    cp, _buf = prob.to_c()
+    k = C.c_int32(0)
+    _check(lib().rd_get_steps_per_launch(C.byref(cp), C.byref(k)))
+    return k.value
 
 
 def set_autotune(enable: bool) -> None:

@@ -110,6 +110,7 @@ void derive_constants(const rd_problem* p, KConst& c) {
   std::memset(&c, 0, sizeof c);
   c.nx = p->nx;
   c.ny = p->ny;
+  c.ksteps = 1;
   c.sharp = std::isinf(p->step_k) ? 1 : 0;
   c.k = p->step_k;
   c.k6 = c.sharp ? 0.0 : 6.0 * p->step_k;
@@ -189,8 +190,8 @@ void derive_constants(const rd_problem* p, KConst& c) {
 
 // Launch geometry for `ty` rows per wave band: column strips of 64 - 2 ns
 // outputs, bands of ty rows.
-void set_geometry(KConst& c, int ns, int ty) {
-  const int tx = strip_width(ns);
+void set_geometry(KConst& c, int halo, int ty) {
+  const int tx = strip_width(halo);
   c.nsx = (c.nx + tx - 1) / tx;
   ty = std::max(1, std::min(ty, c.ny));
   c.ty = ty;
@@ -234,15 +235,39 @@ int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hip
   return RD_OK;
 }
 
+int max_steps_per_launch(int model, int ns) {
+  return (model == RD_MODEL_DIFFUSION || model == RD_MODEL_BARKLEY) ? 8 / ns : 1;
+}
+static_assert(MultiStep<RD_MODEL_BARKLEY, 1, kModeStep>::max == 8 &&
+                  MultiStep<RD_MODEL_DIFFUSION, 2, kModeStep>::max == 4 &&
+                  MultiStep<RD_MODEL_BARKLEY, 4, kModeStep>::max == 2 &&
+                  MultiStep<RD_MODEL_FENTON_KARMA, 1, kModeStep>::max == 1 &&
+                  MultiStep<RD_MODEL_BARKLEY, 4, kModeTangent>::max == 1,
+              "max_steps_per_launch must agree with MultiStep");
+
 // nsteps fused steps of the packed arrays `a` (np = NV state fields, or 2 NV
 // with the tangent fields after them), in place, ping-ponging through the
 // equally sized buffers `b`; optional state checkpoints every `every` steps.
+// Launches advance c.ksteps steps where that neither passes nsteps nor a
+// checkpoint, and one step otherwise.
 int run_steps(const rd_problem* p, const KConst& c, bool tangent, double* const* a,
               double* const* b, int64_t nsteps, double* checkpoints, int every, hipStream_t s) {
   const int nv = n_fields(p->model);
   const int np = tangent ? 2 * nv : nv;
   const size_t cells = (size_t)p->nx * (size_t)p->ny;
   const size_t bytes = cells * sizeof(double);
+  const int K = tangent ? 1 : std::max(c.ksteps, 1);
+  KConst c1 = c;  // one step per launch
+  c1.ksteps = 1;
+  set_geometry(c1, n_stages(p->scheme), c.ty);
+  const bool ck = checkpoints && every > 0;
+  auto chunk = [&](int64_t n) -> int {
+    if (K > 1 && n + K <= nsteps && (!ck || n % every + K <= every)) return K;
+    return 1;
+  };
+  int64_t launches = 0;
+  for (int64_t n = 0; n < nsteps; n += chunk(n)) ++launches;
+
   double* bufA[kMaxPacked];
   double* bufB[kMaxPacked];
   for (int f = 0; f < np; ++f) {
@@ -251,7 +276,7 @@ int run_steps(const rd_problem* p, const KConst& c, bool tangent, double* const*
   }
   double** cur = bufA;
   double** oth = bufB;
-  if (nsteps % 2 == 1) {
+  if (launches % 2 == 1) {  // an odd number of launches must end in the caller's arrays
     int rc = copy_state(bufB, bufA, np, bytes, s);
     if (rc) return rc;
     cur = bufB;
@@ -259,14 +284,15 @@ int run_steps(const rd_problem* p, const KConst& c, bool tangent, double* const*
   }
   SweepArgs args;
   std::memset(&args, 0, sizeof args);
-  args.c = c;
-  for (int64_t n = 0; n < nsteps; ++n) {
-    if (checkpoints && every > 0 && n % every == 0) {
+  for (int64_t n = 0; n < nsteps;) {
+    if (ck && n % every == 0) {
       double* dst[kMaxFields];
       for (int f = 0; f < nv; ++f) dst[f] = checkpoints + ((size_t)(n / every) * nv + f) * cells;
       int rc = copy_state(dst, cur, nv, bytes, s);
       if (rc) return rc;
     }
+    const int kk = chunk(n);
+    args.c = kk == K ? c : c1;
     for (int f = 0; f < np; ++f) {
       args.in[f] = cur[f];
       args.out[f] = oth[f];
@@ -274,6 +300,7 @@ int run_steps(const rd_problem* p, const KConst& c, bool tangent, double* const*
     hipError_t e = launch_sweep_mode(tangent ? kModeTangent : kModeStep, p->model, p->stencil, p->scheme, args, s);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     std::swap(cur, oth);
+    n += kk;
   }
   return RD_OK;
 }
@@ -284,12 +311,14 @@ void plan_geometry(const rd_problem* p, KConst& c, bool tangent, double* const* 
                    double* const* out, hipStream_t s) {
   const int ns = n_stages(p->scheme);
   const int np = (tangent ? 2 : 1) * n_fields(p->model);
+  const int kmax = tangent ? 1 : max_steps_per_launch(p->model, ns);
   auto trial = [&](Plan pl) {
     SweepArgs a;
     std::memset(&a, 0, sizeof a);
     a.c = c;
     a.c.variant = pl.variant;
-    set_geometry(a.c, ns, pl.ty);
+    a.c.ksteps = pl.k;
+    set_geometry(a.c, ns * pl.k, pl.ty);
     for (int f = 0; f < np; ++f) {
       a.in[f] = in[f];
       a.out[f] = out[f];
@@ -297,9 +326,10 @@ void plan_geometry(const rd_problem* p, KConst& c, bool tangent, double* const* 
     return launch_sweep_mode(tangent ? kModeTangent : kModeStep, p->model, p->stencil, p->scheme, a, s);
   };
   const Plan pl = tuned_plan(tangent ? kTuneTangent : kTuneForward, p->model, p->stencil, p->scheme,
-                             p->nx, p->ny, ns, s, trial, true);
+                             p->nx, p->ny, ns, s, trial, true, 0, 0, kmax);
   c.variant = pl.variant;
-  set_geometry(c, ns, pl.ty);
+  c.ksteps = pl.k;
+  set_geometry(c, ns * pl.k, pl.ty);
 }
 
 int check_workspace(void* ws, size_t ws_bytes, size_t need) {

@@ -72,11 +72,30 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
   derive_constants(p, c);
   // recompute and stage-input launches use the forward step's plan; the
   // adjoint kernel its own band height
-  const Plan fp = current_plan(kTuneForward, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true);
+  const Plan fp = current_plan(kTuneForward, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true,
+                               max_steps_per_launch(p->model, ns));
   KConst cf = c;
   cf.variant = fp.variant;
+  cf.ksteps = 1;  // every intermediate state is needed
   set_geometry(cf, ns, fp.ty);
-  set_geometry(c, ns, current_rows(kTuneAdjoint, p->model, p->stencil, p->scheme, p->nx, p->ny, ns));
+  // Adjoint band height: tuned on first use with trial launches that read the
+  // caller's cotangent and first checkpoint and write only workspace (before
+  // the workspace holds anything).
+  auto adj_trial = [&](int ty) -> hipError_t {
+    AdjArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.c = c;
+    set_geometry(a.c, ns, ty);
+    for (int f = 0; f < nv; ++f) {
+      a.z[f] = ckpt(0, f);
+      a.lam_in[f] = cot[f];
+      a.lam_out[f] = lam_buf[f];
+    }
+    for (int i = 0; i < ns - 1; ++i)
+      for (int f = 0; f < nv; ++f) a.ys[i][f] = stage_in(i, f);
+    return launch_adjoint_kernel(p->model, p->stencil, p->scheme, a, s);
+  };
+  set_geometry(c, ns, tuned_rows(kTuneAdjoint, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, s, adj_trial));
 
   double* curA[kMaxFields];
   double* curB[kMaxFields];

@@ -45,6 +45,7 @@ struct KConst {
   int nsx, nby, ty;  // launch geometry: column strips, row bands, rows per band
   int sharp;         // 1: Heaviside step instead of H_k
   int variant;       // fused-step kernel variant (StepVariant)
+  int ksteps;        // steps per launch of the state-only sweep (1, 2, 4, 8)
   double k;          // H_k sharpness (+inf for the Heaviside step)
   double k6;         // dH_k/dt scale 6 k (0 for the Heaviside step)
   double dt, h2, h6; // dt, dt/2, dt/6

@@ -15,7 +15,8 @@ int n_stages(int scheme);
 int validate(const rd_problem* p);
 int validate_fields(const rd_problem* p, double* const* f, const char* what);
 void derive_constants(const rd_problem* p, KConst& c);
-void set_geometry(KConst& c, int ns, int ty);
+// Strips and bands for `halo` = stages per launch (NS times steps per launch).
+void set_geometry(KConst& c, int halo, int ty);
 
 // Autotuned rows per wave band (rd_tune.cpp).  `trial(ty)` enqueues one
 // launch with that band height that writes only workspace.
@@ -23,15 +24,20 @@ enum TuneKind { kTuneForward = 0, kTuneTangent = 1, kTuneAdjoint = 2, kTuneBatch
 struct Plan {
   int variant;  // StepVariant
   int ty;       // rows per band
+  int k = 1;    // steps per launch (state-only sweep)
 };
+// Largest steps-per-launch the state-only sweep supports for this model and
+// scheme (1: none).
+int max_steps_per_launch(int model, int ns);
 // Tunes kernel variant and band height together (trial launches write only
 // workspace); allow_pipe = false restricts to the sweep kernel.  shape_key
 // distinguishes launches whose grids nx x ny do not describe (batches);
 // fallback_ty > 0 replaces the single-grid heuristic's band height.
 Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
                 const std::function<hipError_t(Plan)>& trial, bool allow_pipe, int shape_key = 0,
-                int fallback_ty = 0);
-Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe);
+                int fallback_ty = 0, int kmax = 1);
+Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe,
+                  int kmax = 1);
 int heuristic_rows(int nx, int ny, int ns);
 // Override, else cached tuning result, else heuristic (never tunes).
 int current_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int ns);

@@ -59,12 +59,21 @@ template <> struct Scheme<4> {
   __device__ static double next_coef(const KConst& c, int s) { return s < 3 ? c.h2 : c.dt; }
 };
 
+// Steps one launch may advance (temporal blocking): the state-only sweep of
+// the models with cheap reactions chains up to 8 stages, so that a launch
+// reads and writes the state once for several steps.  1 elsewhere.
+template <int MODEL, int NS, int MODE> struct MultiStep {
+  static constexpr int max =
+      MODE == kModeStep && (MODEL == RD_MODEL_DIFFUSION || MODEL == RD_MODEL_BARKLEY) ? 8 / NS : 1;
+};
+
 // Waves per SIMD each kernel's register budget is sized for (the largest
-// count that still needs no scratch spills once the four stages of a steady
-// RK4 iteration are interleaved).
-template <int MODEL, int STENCIL, int NS, int MODE> struct SweepOccupancy {
+// count that still needs no scratch spills once the stages of a steady
+// iteration are interleaved).
+template <int MODEL, int STENCIL, int NS, int MODE, int K = 1> struct SweepOccupancy {
   static constexpr bool heavy = MODEL == RD_MODEL_BOCF && STENCIL == RD_LAP9_ANISO;
-  static constexpr int value = MODE == kModeTangent ? (NS == 4 || (NS == 2 && MODEL == RD_MODEL_BOCF) ? 1 : 2)
+  static constexpr int value = K > 1                ? 2
+                               : MODE == kModeTangent ? (NS == 4 || (NS == 2 && MODEL == RD_MODEL_BOCF) ? 1 : 2)
                                : NS == 4            ? (heavy ? 1 : 2)
                                : NS == 2 && heavy   ? 2
                                                     : 3;
@@ -88,17 +97,25 @@ template <int MODEL, int NS, int MODE> struct SweepPrefetch {
 
 // One wavefront's share of a sweep: strip wid / nby, band wid % nby of the
 // grid described by c, reading `in` and writing `out` (or the stage inputs
-// `ys`).  Shared by the single-grid and the batched kernels.
-template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE>
+// `ys`), advancing K steps (K > 1 only for the plain step).  Shared by the
+// single-grid and the batched kernels.
+//
+// K steps chain K copies of the one-step pipeline: copy k takes row r - k NS
+// of z_{n+k} (the row copy k - 1 finished in the same iteration; copy 0 the
+// row just loaded) and runs its stage s on row r - k NS - s, so the launch
+// needs KS = K NS halo columns and ramp rows.
+template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1>
 __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double* const* out,
                                                 double* const (*ys)[kMaxFields], const KConst& c,
                                                 int wid) {
+  static_assert(K == 1 || MODE == kModeStep, "several steps per launch advance the state only");
   constexpr bool TAN = MODE == kModeTangent;
   constexpr bool STAGES = MODE == kModeStages;
   constexpr int NV = ModelTraits<MODEL>::NV;
   constexpr int NF = TAN ? 2 * NV : NV;  // values per cell carried
   constexpr int ND = TAN ? 2 : 1;        // diffusive components: u (and du)
-  constexpr int TX = kWave - 2 * NS;
+  constexpr int KS = K * NS;             // stages per launch
+  constexpr int TX = kWave - 2 * KS;
   constexpr int ZR = (NS + 1 > 3) ? NS + 1 : 3;
   auto comp = [](int d) { return d == 0 ? 0 : NV; };  // index of diffusive component d
   auto diffusive = [](int f) { return f == 0 || (TAN && f == NV); };
@@ -106,37 +123,42 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   const int lane = threadIdx.x & (kWave - 1);
   const int sx = wid / c.nby;  // bands of one strip are consecutive
   const int by = wid % c.nby;
-  const int gx = sx * TX - NS + lane;
+  const int gx = sx * TX - KS + lane;
   const int cx = min(max(gx, 0), c.nx - 1);
-  const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;
+  const bool out_col = lane >= KS && lane < KS + TX && gx < c.nx;
   const Column col = make_column(gx, c, STENCIL == RD_LAP9_ANISO);
 
   const int yA = by * c.ty;
   const int yB = min(yA + c.ty, c.ny);
-  const int r_first = max(yA - NS, 0);
-  const int r_last = yB - 1 + NS;
-  const int load_end = min(yB + NS, c.ny);
+  const int r_first = max(yA - KS, 0);
+  const int r_last = yB - 1 + KS;
+  const int load_end = min(yB + KS, c.ny);
   const size_t nx = (size_t)c.nx;
 
-  double zr[ZR][NF];          // zr[a] = z_n at row r - a
-  double acc[NS][NF];         // acc[s-1] = running stage sum of row r - s
-  double yu[NS + 1][3][ND];   // stage-s input u (du) at rows r-s+1, r-s, r-s-1
-  double yg[NS + 1][NF];      // stage-s input, other components, row r - s
-  double ygn[NS + 1][NF];     // ... produced this iteration for row r-s+1
+  // Per step copy k: register rings indexed by rows relative to its input row
+  // r - k NS.
+  double zr[K][ZR][NF];          // z_{n+k} at row (r - k NS) - a
+  double acc[K][NS][NF];         // running stage sum of row (r - k NS) - s
+  double yu[K][NS + 1][3][ND];   // stage-s input u (du), rows (r - k NS) - s + 1 .. - s - 1
+  double yg[K][NS + 1][NF];      // stage-s input, other components, row (r - k NS) - s
+  double ygn[K][NS + 1][NF];     // ... produced this iteration for the row below it
 #pragma unroll
-  for (int k = 0; k < ZR; ++k)
+  for (int k = 0; k < K; ++k) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) zr[k][f] = 0.0;
+    for (int a = 0; a < ZR; ++a)
 #pragma unroll
-  for (int k = 0; k < NS; ++k)
+      for (int f = 0; f < NF; ++f) zr[k][a][f] = 0.0;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) acc[k][f] = 0.0;
+    for (int a = 0; a < NS; ++a)
 #pragma unroll
-  for (int s = 0; s <= NS; ++s) {
+      for (int f = 0; f < NF; ++f) acc[k][a][f] = 0.0;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) yu[s][0][d] = yu[s][1][d] = yu[s][2][d] = 0.0;
+    for (int s = 0; s <= NS; ++s) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f) yg[s][f] = ygn[s][f] = 0.0;
+      for (int d = 0; d < ND; ++d) yu[k][s][0][d] = yu[k][s][1][d] = yu[k][s][2][d] = 0.0;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) yg[k][s][f] = ygn[k][s][f] = 0.0;
+    }
   }
 
   // Rows are prefetched PF iterations ahead, so that PF iterations of
@@ -157,40 +179,43 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
     }
   }
 
-  // One iteration: take row r, run stage s on row r - s.  STEADY marks
-  // iterations in which every stage is active and the rows involved are
-  // interior (no y-mirror): its body is free of branches, so the independent
-  // reactions of the stages can be interleaved.  SLOT < 0: the prefetch ring
-  // shifts by one row (pre[0] is row r); SLOT = q: the loop is unrolled by PF
-  // and slot q holds row r, so no prefetched register is read before its
-  // turn (a shift would wait for the youngest load).
+  // One iteration: take row r; step copy k runs stage s on row r - k NS - s.
+  // STEADY marks iterations in which every stage is active and the rows
+  // involved are interior (no y-mirror): its body is free of branches, so the
+  // independent reactions of the stages can be interleaved.  SLOT < 0: the
+  // prefetch ring shifts by one row (pre[0] is row r); SLOT = q: the loop is
+  // unrolled by PF and slot q holds row r, so no prefetched register is read
+  // before its turn (a shift would wait for the youngest load).
   auto iter = [&](int r, auto steady_tag, auto slot_tag) __attribute__((always_inline)) {
     constexpr bool STEADY = decltype(steady_tag)::value;
     constexpr int SLOT = decltype(slot_tag)::value;
     // Advance the register rings by one row.
 #pragma unroll
-    for (int k = ZR - 1; k > 0; --k)
+    for (int k = 0; k < K; ++k) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) zr[k][f] = zr[k - 1][f];
+      for (int a = ZR - 1; a > 0; --a)
 #pragma unroll
-    for (int k = NS - 1; k > 0; --k)
+        for (int f = 0; f < NF; ++f) zr[k][a][f] = zr[k][a - 1][f];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) acc[k][f] = acc[k - 1][f];
+      for (int a = NS - 1; a > 0; --a)
 #pragma unroll
-    for (int s = 2; s <= NS; ++s) {
+        for (int f = 0; f < NF; ++f) acc[k][a][f] = acc[k][a - 1][f];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        yu[s][2][d] = yu[s][1][d];
-        yu[s][1][d] = yu[s][0][d];
+      for (int s = 2; s <= NS; ++s) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          yu[k][s][2][d] = yu[k][s][1][d];
+          yu[k][s][1][d] = yu[k][s][0][d];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          if (!diffusive(f)) yg[k][s][f] = ygn[k][s][f];
       }
-#pragma unroll
-      for (int f = 0; f < NF; ++f)
-        if (!diffusive(f)) yg[s][f] = ygn[s][f];
     }
     if (STEADY || r < load_end) {
       constexpr int q = SLOT < 0 ? 0 : SLOT;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) zr[0][f] = pre[q][f];
+      for (int f = 0; f < NF; ++f) zr[0][0][f] = pre[q][f];
       if constexpr (SLOT < 0) {
 #pragma unroll
         for (int p = 0; p + 1 < PF; ++p)
@@ -202,100 +227,122 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
       for (int f = 0; f < NF; ++f) pre[SLOT < 0 ? PF - 1 : q][f] = in[f][o];
     }
 
+    double zout[NF];  // row r - (k + 1) NS of z_{n+k+1}, handed to copy k + 1
 #pragma unroll
-    for (int s = 1; s <= NS; ++s) {
-      if (STAGES && s == NS) continue;  // k_NS is not a stage input
-      const int rho = r - s;
-      if (!STEADY) {
-        const int lo = max(yA - (NS - s), 0);
-        const int hi = min(yB + (NS - s), c.ny);
-        if (rho < lo || rho >= hi) continue;  // wave-uniform
+    for (int f = 0; f < NF; ++f) zout[f] = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (k > 0) {
+        // the row copy k - 1 finished this iteration (read only inside the
+        // range that copy produced)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) zr[k][0][f] = zout[f];
       }
+#pragma unroll
+      for (int s = 1; s <= NS; ++s) {
+        if (STAGES && s == NS) continue;  // k_NS is not a stage input
+        const int rho = r - k * NS - s;
+        if (!STEADY) {
+          const int lo = max(yA - (K - k) * NS + s, 0);
+          const int hi = min(yB + (K - k) * NS - s, c.ny);
+          if (rho < lo || rho >= hi) continue;  // wave-uniform
+        }
 
-      double y[NF], up[ND], dn[ND];
-      if (s == 1) {
+        double y[NF], up[ND], dn[ND];
+        if (s == 1) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) y[f] = zr[1][f];
+          for (int f = 0; f < NF; ++f) y[f] = zr[k][1][f];
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          up[d] = zr[2][comp(d)];
-          dn[d] = zr[0][comp(d)];
+          for (int d = 0; d < ND; ++d) {
+            up[d] = zr[k][2][comp(d)];
+            dn[d] = zr[k][0][comp(d)];
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; ++f)
+            if (!diffusive(f)) y[f] = yg[k][s][f];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            y[comp(d)] = yu[k][s][1][d];
+            up[d] = yu[k][s][2][d];
+            dn[d] = yu[k][s][0][d];
+          }
         }
-      } else {
+        if (!STEADY) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
-          if (!diffusive(f)) y[f] = yg[s][f];
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          y[comp(d)] = yu[s][1][d];
-          up[d] = yu[s][2][d];
-          dn[d] = yu[s][0][d];
+          for (int d = 0; d < ND; ++d) {
+            if (rho == 0) up[d] = y[comp(d)];
+            if (rho == c.ny - 1) dn[d] = y[comp(d)];
+          }
         }
-      }
-      if (!STEADY) {
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          if (rho == 0) up[d] = y[comp(d)];
-          if (rho == c.ny - 1) dn[d] = y[comp(d)];
-        }
-      }
 
-      double lap[ND];
+        double lap[ND];
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
-        lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c);
-      double k[NF];
-      eval_rates<MODEL, TAN>(c, y, k);
+        for (int d = 0; d < ND; ++d)
+          lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c);
+        double kr[NF];
+        eval_rates<MODEL, TAN>(c, y, kr);
 #pragma unroll
-      for (int d = 0; d < ND; ++d) k[comp(d)] = lap[d] + k[comp(d)];
+        for (int d = 0; d < ND; ++d) kr[comp(d)] = lap[d] + kr[comp(d)];
 
-      // the last stage's row lies inside the band in every steady iteration
-      const bool last_core = out_col && (STEADY || (rho >= yA && rho < yB));
-      if (NS == 1) {
-        if (!STAGES && last_core) {
-          const size_t o = (size_t)rho * nx + gx;
+        // the last stage's row lies inside the band in every steady iteration
+        const bool last = k == K - 1;
+        const bool last_core = out_col && (STEADY || (rho >= yA && rho < yB));
+        if (NS == 1) {
+          if (STAGES) continue;
+          if (!last) {
 #pragma unroll
-          for (int f = 0; f < NF; ++f) out[f][o] = zr[1][f] + c.dt * k[f];
+            for (int f = 0; f < NF; ++f) zout[f] = zr[k][1][f] + c.dt * kr[f];
+          } else if (last_core) {
+            const size_t o = (size_t)rho * nx + gx;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) out[f][o] = zr[k][1][f] + c.dt * kr[f];
+          }
+          continue;
         }
-        continue;
-      }
-      // stage sum: k1, then + 2 k_s (RK4 middle stages) or + k_s
+        // stage sum: k1, then + 2 k_s (RK4 middle stages) or + k_s
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        if (s == 1) acc[0][f] = k[f];
-        else if (NS == 4 && s < 4) acc[s - 1][f] = acc[s - 1][f] + 2.0 * k[f];
-        else acc[s - 1][f] = acc[s - 1][f] + k[f];
-      }
-      if (s < NS) {
-        const double cs = Scheme<NS>::next_coef(c, s);
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-          if (!diffusive(f)) ygn[s + 1][f] = zr[s][f] + cs * k[f];
-#pragma unroll
-        for (int d = 0; d < ND; ++d) yu[s + 1][0][d] = zr[s][comp(d)] + cs * k[comp(d)];
-        if (STAGES && out_col && rho >= yA && rho < yB) {
-          const size_t o = (size_t)rho * nx + gx;
-          ys[s - 1][0][o] = yu[s + 1][0][0];
-#pragma unroll
-          for (int f = 1; f < NV; ++f) ys[s - 1][f][o] = ygn[s + 1][f];
+        for (int f = 0; f < NF; ++f) {
+          if (s == 1) acc[k][0][f] = kr[f];
+          else if (NS == 4 && s < 4) acc[k][s - 1][f] = acc[k][s - 1][f] + 2.0 * kr[f];
+          else acc[k][s - 1][f] = acc[k][s - 1][f] + kr[f];
         }
-      } else if (!STAGES && last_core) {
-        const double bw = NS == 4 ? c.h6 : c.h2;
-        const size_t o = (size_t)rho * nx + gx;
+        if (s < NS) {
+          const double cs = Scheme<NS>::next_coef(c, s);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) out[f][o] = zr[s][f] + bw * acc[s - 1][f];
+          for (int f = 0; f < NF; ++f)
+            if (!diffusive(f)) ygn[k][s + 1][f] = zr[k][s][f] + cs * kr[f];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) yu[k][s + 1][0][d] = zr[k][s][comp(d)] + cs * kr[comp(d)];
+          if (STAGES && out_col && rho >= yA && rho < yB) {
+            const size_t o = (size_t)rho * nx + gx;
+            ys[s - 1][0][o] = yu[k][s + 1][0][0];
+#pragma unroll
+            for (int f = 1; f < NV; ++f) ys[s - 1][f][o] = ygn[k][s + 1][f];
+          }
+        } else if (!STAGES) {
+          const double bw = NS == 4 ? c.h6 : c.h2;
+          if (!last) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) zout[f] = zr[k][s][f] + bw * acc[k][s - 1][f];
+          } else if (last_core) {
+            const size_t o = (size_t)rho * nx + gx;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) out[f][o] = zr[k][s][f] + bw * acc[k][s - 1][f];
+          }
+        }
       }
     }
   };
 
-  // Steady iterations: r >= yA + NS (every stage's row is at or past its
-  // band start), r >= NS + 1 (no stage on row 0), r < min(yB + NS, ny) (row r
-  // is an input row, so no stage runs on row ny - 1 or past its band end).
+  // Steady iterations: r >= yA + KS (every stage's row is at or past its
+  // range start), r >= KS + 1 (no stage on row 0), r < min(yB + KS, ny) (row r
+  // is an input row, so no stage runs on row ny - 1 or past its range end).
   // Ramp-up and ramp-down iterations shift the prefetch ring; the steady run
   // between them goes PF rows at a time with fixed slots (its rows r + q sit
   // in slot q because the ring is in order when the run starts and ends).
   using Shift = std::integral_constant<int, -1>;
-  const int ss_lo = min(max(yA + NS, NS + 1), r_last + 1);
+  const int ss_lo = min(max(yA + KS, KS + 1), r_last + 1);
   const int ss_hi = max(load_end, ss_lo);
   const int ss_end = ss_lo + (ss_hi - ss_lo) / PF * PF;
   int r = r_first;
@@ -312,34 +359,47 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 }
 
 // Strips that touch the grid's x-edges apply the mirror; interior strips skip it.
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int K = 1>
 __device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
                                            double* const (*ys)[kMaxFields], const KConst& c,
                                            int wid) {
-  const int x0 = (wid / c.nby) * (kWave - 2 * NS) - NS;
+  const int x0 = (wid / c.nby) * (kWave - 2 * K * NS) - K * NS;
   if (strip_touches_edge(x0, c))
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K>(in, out, ys, c, wid);
   else
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K>(in, out, ys, c, wid);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int K>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
+__attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE, K>::value)))
 void sweep_kernel(SweepArgs a) {
   const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
   const int wid = __builtin_amdgcn_readfirstlane(blk * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (wid >= a.c.nsx * a.c.nby) return;  // whole waves only: no barrier follows
-  sweep_wave<MODEL, STENCIL, NS, MODE>(a.in, a.out, a.ys, a.c, wid);
+  sweep_wave<MODEL, STENCIL, NS, MODE, K>(a.in, a.out, a.ys, a.c, wid);
 }
 
+template <int MODEL, int STENCIL, int NS, int MODE, int K>
+hipError_t launch_sweep_k(const SweepArgs& a, hipStream_t stream) {
+  const int waves = a.c.nsx * a.c.nby;
+  const int blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE, K>), dim3(blocks), dim3(256), 0, stream, a);
+  return hipGetLastError();
+}
+
+// One launch of a.c.ksteps steps (1 unless MultiStep allows more).
 template <int MODEL, int STENCIL, int NS, int MODE>
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
   if (MODE == kModeStages && NS == 1) return hipSuccess;  // Euler has no inner stage
-  const int waves = a.c.nsx * a.c.nby;
-  const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE>), dim3(blocks), dim3(256), 0, stream, a);
-  return hipGetLastError();
+  constexpr int KMAX = MultiStep<MODEL, NS, MODE>::max;
+  switch (a.c.ksteps) {
+    case 1: return launch_sweep_k<MODEL, STENCIL, NS, MODE, 1>(a, stream);
+    case 2: if constexpr (KMAX >= 2) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 2>(a, stream); break;
+    case 4: if constexpr (KMAX >= 4) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 4>(a, stream); break;
+    case 8: if constexpr (KMAX >= 8) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 8>(a, stream); break;
+  }
+  return hipErrorInvalidValue;
 }
 
 // Dispatch over stencil and scheme for one model and mode.

@@ -19,14 +19,20 @@ namespace rd {
 
 namespace {
 std::mutex g_mu;
-// Keyed by the problem and by the overrides in force: a fixed variant or band
-// height restricts the candidates, so it selects its own cache entry.
-using Key = std::tuple<int, int, int, int, int, int, int, int, int>;
+// Keyed by the problem and by the overrides in force: a fixed variant, band
+// height or step count restricts the candidates, so it selects its own entry.
+using Key = std::tuple<int, int, int, int, int, int, int, int, int, int>;
 std::map<Key, Plan> g_cache;
 bool g_enabled = true;
 int g_override = -1;          // rows per band (> 0: fixed)
 int g_variant_override = -1;  // kernel variant (>= 0: fixed)
+int g_ksteps_override = -1;   // steps per launch (> 0: fixed, capped by the model's maximum)
 }  // namespace
+
+void set_ksteps_override(int k) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_ksteps_override = k;
+}
 
 void set_tile_rows_override(int rows) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -65,15 +71,24 @@ static Plan heuristic_plan(int nx, int ny, int ns, int variant) {
   return Plan{kVariantPipe, ty < ny ? ty : ny};
 }
 
-static Plan apply_overrides(Plan p, int ny) {
+// Steps per launch a fixed override asks for, within [1, kmax].
+static int fixed_k(int kmax) {
+  if (g_ksteps_override <= 0) return 0;
+  return g_ksteps_override < kmax ? g_ksteps_override : kmax;
+}
+
+static Plan apply_overrides(Plan p, int ny, int kmax) {
   if (g_variant_override >= 0) p.variant = g_variant_override;
   if (g_override > 0) p.ty = g_override < ny ? g_override : ny;
+  // several steps per launch exist only in the sweep kernel
+  if (fixed_k(kmax) > 1 && g_variant_override != kVariantPipe) p.variant = kVariantSweep;
+  if (fixed_k(kmax) > 0 && p.variant == kVariantSweep) p.k = fixed_k(kmax);
   return p;
 }
 
 Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, hipStream_t s,
                 const std::function<hipError_t(Plan)>& trial, bool allow_pipe, int shape_key,
-                int fallback_ty) {
+                int fallback_ty, int kmax) {
   bool tune;
   Plan fallback;
   std::vector<Plan> cands;
@@ -81,19 +96,24 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
   {
     std::lock_guard<std::mutex> lk(g_mu);
     const int vfix = allow_pipe ? g_variant_override : kVariantSweep;
-    key = Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0, shape_key);
+    const int kfix = fixed_k(kmax);
+    key = Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0, shape_key,
+              kmax > 1 ? kfix : 1);
     Plan start = heuristic_plan(nx, ny, ns, vfix);
     if (fallback_ty > 0) start.ty = fallback_ty < ny ? fallback_ty : ny;
-    fallback = apply_overrides(start, ny);
+    fallback = apply_overrides(start, ny, kmax);
     if (!allow_pipe) fallback.variant = kVariantSweep;
-    if (g_override > 0 && vfix >= 0) return fallback;  // fully fixed
+    if (g_override > 0 && vfix >= 0 && (kmax == 1 || kfix > 0)) return fallback;  // fully fixed
     auto it = g_cache.find(key);
     if (it != g_cache.end()) return it->second;
     tune = g_enabled;
     if (vfix != kVariantPipe)
       for (int ty : {2, 3, 4, 6, 8, 10, 12, 16, 24, 32, 48, 64})
-        if (ty <= ny && ty >= ns && (g_override <= 0 || ty == fallback.ty)) cands.push_back(Plan{kVariantSweep, ty});
-    if (allow_pipe && vfix != kVariantSweep)
+        for (int k : {1, 2, 4, 8})
+          if (ty <= ny && ty >= ns && (g_override <= 0 || ty == fallback.ty) && k <= kmax &&
+              (kfix <= 0 || k == kfix))
+            cands.push_back(Plan{kVariantSweep, ty, k});
+    if (allow_pipe && vfix != kVariantSweep && kfix <= 1)
       for (int ty : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96})
         if (ty <= ny && ty >= ns && (g_override <= 0 || ty == fallback.ty)) cands.push_back(Plan{kVariantPipe, ty});
   }
@@ -115,6 +135,7 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
     ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
     float ms = 0.f;
     ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+    ms /= (float)cands[i].k;  // per step
     if (ok && ms < best_ms) {
       best_ms = ms;
       best = cands[i];
@@ -137,12 +158,14 @@ int tuned_rows(int kind, int model, int stencil, int scheme, int nx, int ny, int
                     [&](Plan p) { return trial(p.ty); }, false, shape_key, fallback_ty).ty;
 }
 
-Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe) {
+Plan current_plan(int kind, int model, int stencil, int scheme, int nx, int ny, int ns, bool allow_pipe,
+                  int kmax) {
   std::lock_guard<std::mutex> lk(g_mu);
   const int vfix = allow_pipe ? g_variant_override : kVariantSweep;
-  auto it = g_cache.find(Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0, 0));
+  auto it = g_cache.find(Key(kind, model, stencil, scheme, nx, ny, vfix, g_override > 0 ? g_override : 0, 0,
+                             kmax > 1 ? fixed_k(kmax) : 1));
   if (it != g_cache.end()) return it->second;
-  Plan p = apply_overrides(heuristic_plan(nx, ny, ns, vfix), ny);
+  Plan p = apply_overrides(heuristic_plan(nx, ny, ns, vfix), ny, kmax);
   if (!allow_pipe) p.variant = kVariantSweep;
   return p;
 }
@@ -171,10 +194,28 @@ int rd_get_plan(const rd_problem* p, int32_t op, int32_t* variant, int32_t* rows
     case RD_OP_JVP: kind = rd::kTuneTangent; break;
     default: return rd::fail(RD_EINVAL, "rd_get_plan: op %d has no single-grid plan", op);
   }
-  const rd::Plan pl = rd::current_plan(kind, p->model, p->stencil, p->scheme, p->nx, p->ny,
-                                       rd::n_stages(p->scheme), true);
+  const int ns = rd::n_stages(p->scheme);
+  const rd::Plan pl = rd::current_plan(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true,
+                                       op == RD_OP_STEP ? rd::max_steps_per_launch(p->model, ns) : 1);
   *variant = pl.variant;
   *rows = pl.ty;
+  return RD_OK;
+}
+
+int rd_get_steps_per_launch(const rd_problem* p, int32_t* steps) {
+  int rc = rd::validate(p);
+  if (rc) return rc;
+  if (!steps) return rd::fail(RD_EINVAL, "steps is NULL");
+  const int ns = rd::n_stages(p->scheme);
+  *steps = rd::current_plan(rd::kTuneForward, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true,
+                            rd::max_steps_per_launch(p->model, ns)).k;
+  return RD_OK;
+}
+
+int rd_set_steps_per_launch(int32_t steps) {
+  if (steps > 0 && steps != 1 && steps != 2 && steps != 4 && steps != 8)
+    return rd::fail(RD_EINVAL, "steps per launch %d is not 1, 2, 4 or 8", steps);
+  rd::set_ksteps_override(steps > 0 ? steps : -1);
   return RD_OK;
 }
 
@@ -191,7 +232,8 @@ int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows) {
   }
   const int ns = rd::n_stages(p->scheme);
   *rows = op == RD_OP_VJP ? rd::current_rows(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns)
-                          : rd::current_plan(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true).ty;
+                          : rd::current_plan(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true,
+                                             op == RD_OP_STEP ? rd::max_steps_per_launch(p->model, ns) : 1).ty;
   return RD_OK;
 }
 

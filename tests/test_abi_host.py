@@ -101,3 +101,23 @@ def test_workspace_and_checkpoint_queries():
 def test_zero_steps_is_a_noop_without_device():
     rc, _ = call_step(base_problem(nsteps=0), ws=False)
     assert rc == 0
+
+
+def test_steps_per_launch_knob():
+    L = B.lib()
+    for bad in (3, 5, 16):
+        assert L.rd_set_steps_per_launch(bad) == -1
+        assert "steps per launch" in L.rd_last_error().decode()
+    try:
+        w = ri.workload("barkley_128_euler")
+        pb = rd.Problem.from_workload(w, ri.params_array("barkley"))
+        pf = base_problem()
+        rd.set_steps_per_launch(8)
+        assert rd.get_steps_per_launch(pb) == 8       # Euler chains up to 8 steps
+        pb.scheme = "rk4"
+        assert rd.get_steps_per_launch(pb) == 2       # RK4: 2 steps (8 stages)
+        assert rd.get_steps_per_launch(pf) == 1       # gated models: one step
+        rd.set_steps_per_launch(None)
+        assert rd.get_steps_per_launch(pb) == 1       # untuned start
+    finally:
+        rd.set_steps_per_launch(None)

@@ -78,6 +78,48 @@ def test_kernel_variants_and_band_heights_agree_bitwise(model, stencil, scheme):
         assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
 
 
+@pytest.mark.parametrize("model,stencil,scheme", [("barkley", "lap5", "euler"), ("barkley", "lap9", "heun"),
+                                                  ("barkley", "lap5", "rk4"), ("diffusion", "lap9_aniso", "euler"),
+                                                  ("diffusion", "lap9", "rk4")])
+@pytest.mark.parametrize("nx,ny", [(150, 77), (5, 3), (49, 200)])
+def test_steps_per_launch_agree_bitwise(model, stencil, scheme, nx, ny):
+    """Several steps per launch (temporal blocking) compute the same bits as
+    one step per launch, with checkpoints inside the run and a step count that
+    is no multiple of the chunk."""
+    w = workload(model, stencil, scheme, nx, ny)
+    _, pr = problems(w, nsteps=13, checkpoint_every=5)
+    z0 = ri.random_fields(model, nx, ny, 41)
+    nv = len(z0)
+    outs = []
+    try:
+        for k in (1, 2, 4, 8):
+            rd.set_steps_per_launch(k)
+            for rows in (0, 3, 64):
+                rd.set_tile_rows(rows)
+                ck = torch.zeros(3 * nv * nx * ny, dtype=torch.float64, device="cuda")
+                got = gpu_step(pr, z0, ck)
+                outs.append(got + [ck.cpu().numpy()])
+    finally:
+        rd.set_steps_per_launch(None)
+        rd.set_tile_rows(0)
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
+
+
+def test_barkley_euler_eight_steps_per_launch_matches_oracle_bitwise():
+    w = ri.workload("barkley_128_euler")
+    po, pr = problems(w, nsteps=1000)
+    z0 = ri.initial_condition(w)
+    ref = oracle.step(po, z0, 1000)
+    try:
+        rd.set_steps_per_launch(8)
+        assert rd.get_steps_per_launch(pr) == 8
+        got = gpu_step(pr, z0)
+    finally:
+        rd.set_steps_per_launch(None)
+    assert all(np.array_equal(g, r) for g, r in zip(got, ref))
+
+
 @pytest.mark.parametrize("name,model,n,steps", [
     ("barkley_128_euler", "barkley", None, 1000),          # the full 128^2 workload
     ("fk_1024_rk4", "fk", (160, 120), 1000),
