@@ -183,9 +183,19 @@ def other_workloads(rd, torch, dev):
         for q, f, t in zip(probs, fields, tans):
             rd.jvp(q, f, t)
     sec_s = _timed(torch, stream, per_instance, reps=3)
+    # the same batched call captured once in a HIP graph and replayed
+    gstream = torch.cuda.Stream(dev)
+    gstream.wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gstream):
+        with torch.cuda.graph(graph, stream=gstream):
+            rd.step_batched(probs, fields, tans)
+    stream.wait_stream(gstream)
+    sec_g = _timed(torch, stream, graph.replay, reps=3)
     out["fk_ensemble_64_jvp"] = {"steps": n, "cells": cells, "rate_jvp": cells * n / sec_b,
                                  "rate_forward": cells * n / sec_f, "jvp_over_forward": sec_b / sec_f,
                                  "per_instance_calls_over_batched": sec_s / sec_b,
+                                 "rate_jvp_graph_replay": cells * n / sec_g,
                                  "hbm_frac_jvp": 96 * cells * n / sec_b / HBM_PEAK}
 
     # Adjoint: Barkley 1024^2, RK4, 4000 steps, checkpoints every 64

@@ -32,6 +32,11 @@
  *     then returns a message for the calling thread.  No C++ exception
  *     crosses this interface.
  *   - Distinct pointers passed in one call must not alias.
+ *   - The step entry points enqueue kernel launches and device-to-device
+ *     copies only (no allocation, synchronisation or memset), so a HIP graph
+ *     capture on `hip_stream` records them; replays repeat the call with the
+ *     same pointers.  Inside a capture the autotuner does not time anything:
+ *     make one call outside the capture first so the tuned plan is used.
  */
 #ifndef RD_H
 #define RD_H
