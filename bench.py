@@ -40,14 +40,15 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cells: int):
+def measured_traffic(cells: int, tile_rows: int):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel sources; else None."""
+    taken on the current kernel sources with the band height in use; else
+    None."""
     if not os.path.exists(COUNTERS_FILE):
         return None
     with open(COUNTERS_FILE) as fh:
         c = json.load(fh)
-    if c.get("kernel_sha") != kernel_hash() or c.get("cells") != cells:
+    if c.get("kernel_sha") != kernel_hash() or c.get("cells") != cells or c.get("tile_rows") != tile_rows:
         return None
     return c.get("hbm_bytes_per_launch")
 
@@ -158,7 +159,23 @@ def other_workloads(rd, torch, dev):
     sec = _timed(torch, stream, lambda: rd.step(p, z))
     cells = w["nx"] * w["ny"]
     out["bocf_2048_aniso_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
+                                  "plan": list(rd.get_plan(p, "step")),
                                   "hbm_frac": 64 * cells * n / sec / HBM_PEAK}
+
+    # Beyond the 256 MB last-level cache: Fenton-Karma 4096^2 (3 x 128 MiB per
+    # state), the same scheme, so the traffic really goes to HBM.
+    w = ri.workload("fk_1024_rk4", nx=4096, ny=4096)
+    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    p = rd.Problem.from_workload(w, ri.params_array("fk"), nsteps=2)
+    rd.step(p, z)
+    n = 20
+    p.nsteps = n
+    sec = _timed(torch, stream, lambda: rd.step(p, z))
+    cells = w["nx"] * w["ny"]
+    out["fk_4096_rk4_beyond_llc"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
+                                     "hbm_frac": 48 * cells * n / sec / HBM_PEAK,
+                                     "plan": list(rd.get_plan(p, "step"))}
+    del z
 
     # Ensemble: 64 Fenton-Karma grids (16 each of 256^2 .. 768^2) with tangents
     ws = ri.fk_batch_workloads(nsteps=2)
@@ -303,7 +320,7 @@ def main():
                    "D": w["D_par"], "fields": nv},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": measured_traffic(cells),
+                     "traffic": measured_traffic(cells, tile_rows) if variant == "sweep" else None,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": launch_s * 1e6},
         "roofline_alu": {"bound": "alu", "achieved": FK_RK4_FLOPS * rate / 1e12,
