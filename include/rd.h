@@ -11,14 +11,15 @@
  * diffusion operator as a 5-point or 9-point stencil (Eq. 6) whose
  * out-of-domain points take the adjacent boundary value (Fig. 1), and
  * explicit Euler, Heun or classical fourth-order Runge-Kutta stages
- * (Sect. 3, Sect. 4).  Only the voltage u diffuses.
+ * (Sect. 3, Sect. 4).  The voltage u diffuses; FitzHugh-Nagumo's second
+ * field v diffuses too (Eq. 3).
  *
  * Conventions shared by every entry point
  *   - Fields are FP64, one contiguous array per field ("structure of
  *     arrays"), row-major [ny][nx] with x fastest, 8-byte aligned, on the
  *     current HIP device.  Cell (i, j) has centre ((i + 1/2) dx, (j + 1/2) dx).
  *   - Field order is the model's: Barkley (u, v); Fenton-Karma (u, v, w);
- *     Bueno-Orovio (u, v, w, s); diffusion (u).
+ *     Bueno-Orovio (u, v, w, s); FitzHugh-Nagumo (u, v); diffusion (u).
  *   - All field, tangent, cotangent, checkpoint and workspace pointers are
  *     DEVICE pointers owned by the caller.  rd_problem and its params array
  *     are HOST memory, read during the call only.
@@ -57,12 +58,15 @@ enum rd_model {
   RD_MODEL_FENTON_KARMA = 2, /* 3 fields; params: tau_v+, tau_v1-, tau_v2-,
                                 tau_w+, tau_w-, tau_d, tau_0, tau_r, tau_si,
                                 k_si, u_c_si, u_c, u_v                       */
-  RD_MODEL_BOCF = 3          /* 4 fields (Eq. 5); params: u_o, u_u, theta_v,
+  RD_MODEL_BOCF = 3,         /* 4 fields (Eq. 5); params: u_o, u_u, theta_v,
                                 theta_w, theta_v-, theta_o, tau_v1-, tau_v2-,
                                 tau_v+, tau_w1-, tau_w2-, k_w-, u_w-, tau_w+,
                                 tau_fi, tau_o1, tau_o2, tau_so1, tau_so2,
                                 k_so, u_so, tau_s1, tau_s2, k_s, u_s, tau_si,
                                 tau_w_inf, w_inf_star                        */
+  RD_MODEL_FHN = 4           /* FitzHugh-Nagumo, Eq. (3): 2 fields, both
+                                diffusive (v with delta D_par); params:
+                                delta, eps, a1, a0                           */
 };
 
 /* Explicit schemes (Sect. 3): Euler (1 stage), Heun (2), classical RK4 (4). */

@@ -13,8 +13,9 @@ Layout (whole-grid NumPy arrays of shape (ny, nx), x fastest):
                      9-point Laplacians (Eq. 6), the anisotropic flux form,
                      and the same operators assembled as sparse matrices.
   * ``models``    -- smoothed step H_k (Sect. 2) and the reaction terms
-                     N[z] of Eq. (1): Barkley, Fenton-Karma, Bueno-Orovio
-                     (Eq. 5), and pure diffusion (N = 0).
+                     N[z] of Eq. (1): FitzHugh-Nagumo (Eq. 3, two diffusive
+                     fields), Barkley, Fenton-Karma, Bueno-Orovio (Eq. 5),
+                     and pure diffusion (N = 0).
   * ``integrate`` -- explicit Euler, Heun and classical RK4 (Sect. 3), the
                      tangent-linear map by complex-step differentiation of
                      the forward flow, and the adjoint by explicit
@@ -27,12 +28,12 @@ function are taken on the real part.
 from .problem import Problem
 from .stencils import (ghost_pad, laplacian, lap5, lap9, lap_aniso, fibre_coefficients,
                        laplacian_matrix)
-from .models import smooth_step, reaction, reaction_jacobian, n_fields
-from .integrate import rhs, step, jvp, vjp, step_adjoint, stage_states
+from .models import smooth_step, reaction, reaction_jacobian, n_fields, diffusive_fields
+from .integrate import rhs, step, jvp, vjp, step_adjoint, stage_states, transposed_operators
 
 __all__ = [
     "Problem", "ghost_pad", "laplacian", "lap5", "lap9", "lap_aniso",
     "fibre_coefficients", "laplacian_matrix", "smooth_step", "reaction",
-    "reaction_jacobian", "n_fields", "rhs", "step", "jvp", "vjp",
-    "step_adjoint", "stage_states",
+    "reaction_jacobian", "n_fields", "diffusive_fields", "rhs", "step", "jvp", "vjp",
+    "step_adjoint", "stage_states", "transposed_operators",
 ]

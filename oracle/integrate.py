@@ -9,7 +9,9 @@ then the local reaction terms, and combines them in an Euler-like update.
   RK4   : k1 = f(z), k2 = f(z + (dt/2) k1), k3 = f(z + (dt/2) k2),
           k4 = f(z + dt k3),                           z' = z + (dt/6)(k1 + 2 k2 + 2 k3 + k4)
 
-with f(z) = (L u + N_u(z), N_h(z)): only the voltage u diffuses.
+with f(z) = (L u + N_u(z), N_h(z)): only the voltage u diffuses, except in
+FitzHugh-Nagumo (Eq. 3), where v diffuses too, with the operator scaled by
+delta.
 
 Tangent-linear map: the exact derivative of the discrete flow, obtained by
 running the same forward code in complex arithmetic from z + i h dz and
@@ -28,16 +30,22 @@ from __future__ import annotations
 
 import numpy as np
 
-from .models import n_fields, reaction, reaction_jacobian
+from .models import diffusive_fields, n_fields, reaction, reaction_jacobian
 from .problem import Problem
 from .stencils import laplacian, laplacian_matrix
 
 
 def rhs(prob: Problem, z):
-    """f(z): diffusion on the voltage field plus the pointwise reaction."""
-    lap = laplacian(prob, z[0])
-    n = reaction(prob, z)
-    return [lap + n[0]] + list(n[1:])
+    """f(z): diffusion on the diffusive fields plus the pointwise reaction."""
+    n = list(reaction(prob, z))
+    for f, rel in diffusive_fields(prob):
+        n[f] = laplacian(prob, z[f], rel) + n[f]
+    return n
+
+
+def transposed_operators(prob: Problem):
+    """{field: L_f^T} for the diffusive fields (sparse)."""
+    return {f: laplacian_matrix(prob, rel).T.tocsr() for f, rel in diffusive_fields(prob)}
 
 
 def _axpy(z, a, k):
@@ -131,14 +139,16 @@ def _jac_transpose(prob: Problem, Lt, y, a):
         for m in range(1, nv):
             acc = acc + jac[m][l] * a[m]
         out.append(acc)
-    out[0] = out[0] + (Lt @ a[0].ravel()).reshape(a[0].shape)
+    for f, lt in Lt.items():
+        out[f] = out[f] + (lt @ a[f].ravel()).reshape(a[f].shape)
     return out
 
 
 def step_adjoint(prob: Problem, z, lam, Lt=None):
-    """lam_n = (dPhi/dz at z_n)^T lam_{n+1} for one step."""
+    """lam_n = (dPhi/dz at z_n)^T lam_{n+1} for one step; Lt as returned by
+    `transposed_operators`."""
     if Lt is None:
-        Lt = laplacian_matrix(prob).T.tocsr()
+        Lt = transposed_operators(prob)
     A, B = _coefficients(prob)
     ys = stage_states(prob, z)
     S = len(B)
@@ -160,7 +170,7 @@ def vjp(prob: Problem, z0, lam_T, nsteps: int, checkpoint_every: int = 64):
     _check_state(prob, lam_T)
     nsteps = int(nsteps)
     C = int(checkpoint_every) if checkpoint_every and checkpoint_every > 0 else max(nsteps, 1)
-    Lt = laplacian_matrix(prob).T.tocsr()
+    Lt = transposed_operators(prob)
     ckpts = []
     z = [np.array(a, dtype=np.float64, copy=True) for a in z0]
     for n in range(nsteps):

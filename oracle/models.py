@@ -1,8 +1,10 @@
 """Reaction terms N[z] of Eq. (1) and the smoothed step function H_k.
 
 Marcotte & Grigoriev, Sect. 2.  Each model returns the list of pointwise
-rates (N_u, N_h1, ...) for the state z = (u, h1, ...); the diffusion term
-is added by the integrator to the voltage rate only.
+rates (N_u, N_h1, ...) for the state z = (u, h1, ...); the integrator adds
+the diffusion terms to the rates of the diffusive fields (`diffusive_fields`):
+the voltage u for every model, and also v for FitzHugh-Nagumo (Eq. 3), whose
+second field diffuses with the relative coefficient delta.
 
 Constant divisors (time constants) are applied as multiplications by their
 reciprocals, computed once per call; divisors that depend on u (tau(u)) are
@@ -15,8 +17,8 @@ import numpy as np
 
 from .problem import Problem
 
-_NFIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4}
-_NPARAMS = {"diffusion": 0, "barkley": 3, "fk": 13, "bocf": 28}
+_NFIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4, "fhn": 2}
+_NPARAMS = {"diffusion": 0, "barkley": 3, "fk": 13, "bocf": 28, "fhn": 4}
 
 
 def n_fields(model: str) -> int:
@@ -25,6 +27,17 @@ def n_fields(model: str) -> int:
 
 def n_params(model: str) -> int:
     return _NPARAMS[model]
+
+
+def diffusive_fields(prob: Problem):
+    """[(field index, diffusivity relative to D_par)] of the problem's model.
+
+    Eq. (3): u diffuses with D (the nondimensional 1 of the paper, D_par
+    here) and v with delta D, delta the model's first parameter.  All other
+    models diffuse u alone."""
+    if prob.model == "fhn":
+        return [(0, 1.0), (1, float(prob.params[0]))]
+    return [(0, 1.0)]
 
 
 def smooth_step(x, k: float):
@@ -53,6 +66,16 @@ def _barkley(z, p):
     uth = (v + b) * inv_a
     fu = ((inv_eps * u) * (1.0 - u)) * (u - uth)
     fv = u - v
+    return [fu, fv]
+
+
+def _fitzhugh_nagumo(z, p):
+    """Eq. (3) without its diffusion terms:
+    du = u - v - u^3,  dv = eps (u - a1 v - a0);  params (delta, eps, a1, a0)."""
+    u, v = z
+    _delta, eps, a1, a0 = p
+    fu = (u - v) - (u * u) * u
+    fv = eps * ((u - a1 * v) - a0)
     return [fu, fv]
 
 
@@ -149,6 +172,8 @@ def reaction(prob: Problem, z):
         return [np.zeros_like(z[0])]
     if prob.model == "barkley":
         return _barkley(z, prob.params)
+    if prob.model == "fhn":
+        return _fitzhugh_nagumo(z, prob.params)
     if prob.model == "fk":
         return _fenton_karma(z, prob.params, prob.step_k)
     return _bueno_orovio(z, prob.params, prob.step_k)

@@ -12,7 +12,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-MODELS = ("diffusion", "barkley", "fk", "bocf")
+MODELS = ("diffusion", "barkley", "fk", "bocf", "fhn")
 SCHEMES = ("euler", "heun", "rk4")
 STENCILS = ("lap5", "lap9", "lap9_aniso")
 

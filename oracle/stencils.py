@@ -89,10 +89,11 @@ def fibre_coefficients(prob: Problem):
     return dxx_f, dxy_f, dxy_c, dyy_c
 
 
-def lap_aniso(u: np.ndarray, prob: Problem) -> np.ndarray:
-    """div(D grad u) in conservative flux form with zero boundary-face flux."""
+def lap_aniso(u: np.ndarray, prob: Problem, rel: float = 1.0) -> np.ndarray:
+    """div(rel D grad u) in conservative flux form with zero boundary-face
+    flux; the relative diffusivity rel scales the face-flux divergence."""
     dxx_f, dxy_f, dxy_c, dyy_c = fibre_coefficients(prob)
-    inv_dx2 = 1.0 / (prob.dx * prob.dx)
+    inv_dx2 = rel / (prob.dx * prob.dx)
     n = _neighbours(u)
     ny, nx = u.shape
     up, dn, we, ea = n["N"], n["S"], n["W"], n["E"]
@@ -109,11 +110,12 @@ def lap_aniso(u: np.ndarray, prob: Problem) -> np.ndarray:
     return ((fx_all[:, 1:] - fx_all[:, :-1]) + (fy_all[1:, :] - fy_all[:-1, :])) * inv_dx2
 
 
-def laplacian(prob: Problem, u: np.ndarray) -> np.ndarray:
-    """Diffusion term of the voltage equation for the problem's stencil."""
+def laplacian(prob: Problem, u: np.ndarray, rel: float = 1.0) -> np.ndarray:
+    """Diffusion term of a field with diffusivity rel * D_par (rel = 1: the
+    voltage) for the problem's stencil."""
     if prob.stencil == "lap9_aniso":
-        return lap_aniso(u, prob)
-    c = prob.D_par / (prob.dx * prob.dx)
+        return lap_aniso(u, prob, rel)
+    c = (prob.D_par * rel) / (prob.dx * prob.dx)
     if prob.stencil == "lap5":
         return lap5(u, c)
     return lap9(u, c)
@@ -128,7 +130,8 @@ def _clip(a, n):
     return np.clip(a, 0, n - 1)
 
 
-def laplacian_matrix(prob: Problem) -> sp.csr_matrix:
+def laplacian_matrix(prob: Problem, rel: float = 1.0) -> sp.csr_matrix:
+    """The operator `laplacian(prob, ., rel)` as a sparse matrix."""
     nx, ny = prob.nx, prob.ny
     ncell = nx * ny
     j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
@@ -142,7 +145,7 @@ def laplacian_matrix(prob: Problem) -> sp.csr_matrix:
         vals.append(np.broadcast_to(np.asarray(v, dtype=np.float64), np.shape(r)).copy())
 
     if prob.stencil in ("lap5", "lap9"):
-        c = prob.D_par / (prob.dx * prob.dx)
+        c = (prob.D_par * rel) / (prob.dx * prob.dx)
         axial = [(0, -1), (0, 1), (-1, 0), (1, 0)]
         diag = [(-1, -1), (1, -1), (-1, 1), (1, 1)]
         groups = [(axial, c * (1.0 if prob.stencil == "lap5" else ALPHA_AXIAL))]
@@ -158,7 +161,7 @@ def laplacian_matrix(prob: Problem) -> sp.csr_matrix:
 
     # Anisotropic flux form: L = inv_dx2 * (Dx Gx + Dy Gy).
     dxx_f, dxy_f, dxy_c, dyy_c = fibre_coefficients(prob)
-    inv_dx2 = 1.0 / (prob.dx * prob.dx)
+    inv_dx2 = rel / (prob.dx * prob.dx)
     # x-faces: index f = j * (nx - 1) + i for the face between i and i+1.
     nfx = ny * (nx - 1)
     fj, fi = np.meshgrid(np.arange(ny), np.arange(nx - 1), indexing="ij")

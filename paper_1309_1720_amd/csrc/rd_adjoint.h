@@ -8,7 +8,8 @@
 //     kbar_{j-1} = B_{j-1} lam + a_j Ybar_j
 //   lam_n = lam + Ybar_S + ... + Ybar_1.
 // L is symmetric for the 5- and 9-point stencils with mirrored ghosts, so
-// L^T kbar_u is the same stencil applied to kbar_u.  J_N(Y)^T comes from the
+// L^T kbar_u is the same stencil applied to kbar_u (for every diffusive
+// field, each with its own diffusivity).  J_N(Y)^T comes from the
 // reaction's Jacobian columns, evaluated on dual numbers.
 //
 // The stage inputs Y_2 .. Y_S are produced beforehand by the stage-input mode
@@ -71,6 +72,7 @@ template <int MODEL, int STENCIL, int NS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjOccupancy<MODEL>::value)))
 void adjoint_kernel(AdjArgs a) {
   constexpr int NV = ModelTraits<MODEL>::NV;
+  constexpr int NDF = ModelTraits<MODEL>::NDIFF;  // diffusive fields 0 .. NDF-1
   constexpr int TX = kWave - 2 * NS;
   constexpr int LR = (NS + 1 > 3) ? NS + 1 : 3;  // lambda rows kept: r .. r - LR + 1
   const KConst& c = a.c;
@@ -96,7 +98,7 @@ void adjoint_kernel(AdjArgs a) {
 
   double lr[LR][NV];          // lr[a] = lambda_{n+1} at row r - a
   double lacc[NS][NV];        // lacc[a] = running lambda_n at row r - 1 - a
-  double kbu[NS + 1][3];      // kbar_j,u at rows rho_j + 1, rho_j, rho_j - 1
+  double kbu[NS + 1][3][NDF]; // kbar_j diffusive components at rows rho_j + 1, rho_j, rho_j - 1
   double kbg[NS + 1][NV];     // kbar_j other components at row rho_j
   double kbgn[NS + 1][NV];    // ... produced this iteration
 #pragma unroll
@@ -112,7 +114,9 @@ void adjoint_kernel(AdjArgs a) {
 #pragma unroll
     for (int f = 0; f < NV; ++f) lacc[k][f] = 0.0;
 #pragma unroll
-  for (int k = 0; k <= NS; ++k) kbu[k][0] = kbu[k][1] = kbu[k][2] = 0.0;
+  for (int k = 0; k <= NS; ++k)
+#pragma unroll
+    for (int d = 0; d < NDF; ++d) kbu[k][0][d] = kbu[k][1][d] = kbu[k][2][d] = 0.0;
 
   double pre[NV];
 #pragma unroll
@@ -133,10 +137,13 @@ void adjoint_kernel(AdjArgs a) {
       for (int f = 0; f < NV; ++f) lacc[k][f] = lacc[k - 1][f];
 #pragma unroll
     for (int j = 1; j < NS; ++j) {
-      kbu[j][2] = kbu[j][1];
-      kbu[j][1] = kbu[j][0];
 #pragma unroll
-      for (int f = 1; f < NV; ++f) kbg[j][f] = kbgn[j][f];
+      for (int d = 0; d < NDF; ++d) {
+        kbu[j][2][d] = kbu[j][1][d];
+        kbu[j][1][d] = kbu[j][0][d];
+      }
+#pragma unroll
+      for (int f = NDF; f < NV; ++f) kbg[j][f] = kbgn[j][f];
     }
     if (r < load_end) {
 #pragma unroll
@@ -156,25 +163,35 @@ void adjoint_kernel(AdjArgs a) {
       const int hi = min(yB + (j - 1), c.ny);
       if (rho < lo || rho >= hi) continue;  // wave-uniform
 
-      // kbar_j at rows rho-1, rho, rho+1 (u) and rho (all components)
-      double kb[NV], up, dn;
+      // kbar_j at rows rho-1, rho, rho+1 (diffusive fields) and rho (all)
+      double kb[NV], up[NDF], dn[NDF];
       if (j == NS) {
         const double b = AdjCoef<NS>::B(c, j);
 #pragma unroll
         for (int f = 0; f < NV; ++f) kb[f] = b * lr[lag][f];
-        up = b * lr[lag + 1][0];
-        dn = b * lr[lag - 1][0];
-      } else {
-        kb[0] = kbu[j][1];
 #pragma unroll
-        for (int f = 1; f < NV; ++f) kb[f] = kbg[j][f];
-        up = kbu[j][2];
-        dn = kbu[j][0];
+        for (int d = 0; d < NDF; ++d) {
+          up[d] = b * lr[lag + 1][d];
+          dn[d] = b * lr[lag - 1][d];
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < NDF; ++d) {
+          kb[d] = kbu[j][1][d];
+          up[d] = kbu[j][2][d];
+          dn[d] = kbu[j][0][d];
+        }
+#pragma unroll
+        for (int f = NDF; f < NV; ++f) kb[f] = kbg[j][f];
       }
-      if (rho == 0) up = kb[0];
-      if (rho == c.ny - 1) dn = kb[0];
-      const double lapT = edge ? diffusion<STENCIL, true>(up, kb[0], dn, col, rho, c)
-                               : diffusion<STENCIL, false>(up, kb[0], dn, col, rho, c);
+      double lapT[NDF];
+#pragma unroll
+      for (int d = 0; d < NDF; ++d) {
+        if (rho == 0) up[d] = kb[d];
+        if (rho == c.ny - 1) dn[d] = kb[d];
+        lapT[d] = edge ? diffusion<STENCIL, true>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d])
+                       : diffusion<STENCIL, false>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d]);
+      }
 
       double y[NV];
       const size_t o = (size_t)rho * nx + cx;
@@ -187,7 +204,8 @@ void adjoint_kernel(AdjArgs a) {
       }
       double yb[NV];
       reaction_jt<MODEL>(c, y, kb, yb);
-      yb[0] = yb[0] + lapT;
+#pragma unroll
+      for (int d = 0; d < NDF; ++d) yb[d] = yb[d] + lapT[d];
 
       if (j == NS) {
 #pragma unroll
@@ -199,9 +217,10 @@ void adjoint_kernel(AdjArgs a) {
       if (j > 1) {
         const double b = AdjCoef<NS>::B(c, j - 1);
         const double aj = AdjCoef<NS>::A(c, j);
-        kbu[j - 1][0] = b * lr[lag][0] + aj * yb[0];
 #pragma unroll
-        for (int f = 1; f < NV; ++f) kbgn[j - 1][f] = b * lr[lag][f] + aj * yb[f];
+        for (int d = 0; d < NDF; ++d) kbu[j - 1][0][d] = b * lr[lag][d] + aj * yb[d];
+#pragma unroll
+        for (int f = NDF; f < NV; ++f) kbgn[j - 1][f] = b * lr[lag][f] + aj * yb[f];
       } else if (out_col && rho >= yA && rho < yB) {
         const size_t oo = (size_t)rho * nx + gx;
 #pragma unroll
@@ -240,5 +259,6 @@ hipError_t launch_adjoint_diffusion(int stencil, int scheme, const AdjArgs& a, h
 hipError_t launch_adjoint_barkley(int stencil, int scheme, const AdjArgs& a, hipStream_t s);
 hipError_t launch_adjoint_fk(int stencil, int scheme, const AdjArgs& a, hipStream_t s);
 hipError_t launch_adjoint_bocf(int stencil, int scheme, const AdjArgs& a, hipStream_t s);
+hipError_t launch_adjoint_fhn(int stencil, int scheme, const AdjArgs& a, hipStream_t s);
 
 }  // namespace rd

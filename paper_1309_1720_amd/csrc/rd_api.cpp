@@ -35,6 +35,7 @@ int n_fields(int model) {
     case RD_MODEL_BARKLEY: return 2;
     case RD_MODEL_FENTON_KARMA: return 3;
     case RD_MODEL_BOCF: return 4;
+    case RD_MODEL_FHN: return 2;
   }
   return RD_EINVAL;
 }
@@ -45,6 +46,7 @@ int n_params(int model) {
     case RD_MODEL_BARKLEY: return 3;
     case RD_MODEL_FENTON_KARMA: return 13;
     case RD_MODEL_BOCF: return 28;
+    case RD_MODEL_FHN: return 4;
   }
   return RD_EINVAL;
 }
@@ -87,6 +89,8 @@ int validate(const rd_problem* p) {
   if (p->nparams > 0 && !p->params) return fail(RD_EINVAL, "params is NULL");
   for (int i = 0; i < p->nparams; ++i)
     if (!finite(p->params[i])) return fail(RD_EINVAL, "parameter %d is not finite", i);
+  if (p->model == RD_MODEL_FHN && p->params[0] < 0.0)
+    return fail(RD_EINVAL, "FitzHugh-Nagumo delta (relative diffusivity of v) must be >= 0");
   if (p->checkpoint_every < 0) return fail(RD_EINVAL, "checkpoint_every must be >= 0");
   return RD_OK;
 }
@@ -117,8 +121,10 @@ void derive_constants(const rd_problem* p, KConst& c) {
   c.dt = p->dt;
   c.h2 = p->dt * 0.5;
   c.h6 = p->dt / 6.0;
-  c.cD = p->D_par / (p->dx * p->dx);
-  c.inv_dx2 = 1.0 / (p->dx * p->dx);
+  // relative diffusivities of the diffusive fields: u 1, FitzHugh-Nagumo's v delta
+  const double rel[2] = {1.0, p->model == RD_MODEL_FHN ? p->params[0] : 0.0};
+  for (int d = 0; d < 2; ++d)
+    c.dcoef[d] = p->stencil == RD_LAP9_ANISO ? rel[d] / (p->dx * p->dx) : (p->D_par * rel[d]) / (p->dx * p->dx);
   c.theta0 = p->theta0;
   c.dtheta = p->theta1 - p->theta0;
   c.n_total = (double)p->nx;
@@ -126,6 +132,13 @@ void derive_constants(const rd_problem* p, KConst& c) {
   c.dd = p->D_par - c.d_perp;
   const double* q = p->params;
   switch (p->model) {
+    case RD_MODEL_FHN: {
+      FhnC& m = c.m.fh;  // q = (delta, eps, a1, a0); delta scales dcoef[1]
+      m.eps = q[1];
+      m.a1 = q[2];
+      m.a0 = q[3];
+      break;
+    }
     case RD_MODEL_BARKLEY: {
       BarkleyC& m = c.m.bk;
       m.b = q[1];
@@ -222,6 +235,7 @@ hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const
     case RD_MODEL_BARKLEY: RD_MODE_SWITCH(barkley)
     case RD_MODEL_FENTON_KARMA: RD_MODE_SWITCH(fk)
     case RD_MODEL_BOCF: RD_MODE_SWITCH(bocf)
+    case RD_MODEL_FHN: RD_MODE_SWITCH(fhn)
   }
 #undef RD_MODE_SWITCH
   return hipErrorInvalidValue;
@@ -236,11 +250,12 @@ int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hip
 }
 
 int max_steps_per_launch(int model, int ns) {
-  return (model == RD_MODEL_DIFFUSION || model == RD_MODEL_BARKLEY) ? 8 / ns : 1;
+  return (model == RD_MODEL_DIFFUSION || model == RD_MODEL_BARKLEY || model == RD_MODEL_FHN) ? 8 / ns : 1;
 }
 static_assert(MultiStep<RD_MODEL_BARKLEY, 1, kModeStep>::max == 8 &&
                   MultiStep<RD_MODEL_DIFFUSION, 2, kModeStep>::max == 4 &&
                   MultiStep<RD_MODEL_BARKLEY, 4, kModeStep>::max == 2 &&
+                  MultiStep<RD_MODEL_FHN, 2, kModeStep>::max == 4 &&
                   MultiStep<RD_MODEL_FENTON_KARMA, 1, kModeStep>::max == 1 &&
                   MultiStep<RD_MODEL_BARKLEY, 4, kModeTangent>::max == 1,
               "max_steps_per_launch must agree with MultiStep");

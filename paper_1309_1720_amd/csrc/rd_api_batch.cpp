@@ -16,6 +16,7 @@ static hipError_t launch_batch_kernel(bool tangent, int model, int stencil, int 
     case RD_MODEL_BARKLEY: return launch_batch_barkley(tangent, stencil, scheme, a, s);
     case RD_MODEL_FENTON_KARMA: return launch_batch_fk(tangent, stencil, scheme, a, s);
     case RD_MODEL_BOCF: return launch_batch_bocf(tangent, stencil, scheme, a, s);
+    case RD_MODEL_FHN: return launch_batch_fhn(tangent, stencil, scheme, a, s);
   }
   return hipErrorInvalidValue;
 }

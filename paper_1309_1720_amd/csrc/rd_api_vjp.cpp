@@ -15,6 +15,7 @@ hipError_t launch_adjoint_kernel(int model, int stencil, int scheme, const AdjAr
     case RD_MODEL_BARKLEY: return launch_adjoint_barkley(stencil, scheme, a, s);
     case RD_MODEL_FENTON_KARMA: return launch_adjoint_fk(stencil, scheme, a, s);
     case RD_MODEL_BOCF: return launch_adjoint_bocf(stencil, scheme, a, s);
+    case RD_MODEL_FHN: return launch_adjoint_fhn(stencil, scheme, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -120,6 +120,7 @@ RD_DECLARE_BATCH(diffusion)
 RD_DECLARE_BATCH(barkley)
 RD_DECLARE_BATCH(fk)
 RD_DECLARE_BATCH(bocf)
+RD_DECLARE_BATCH(fhn)
 #undef RD_DECLARE_BATCH
 
 }  // namespace rd

@@ -23,6 +23,7 @@ constexpr double kAlphaDiag = 1.0 / 6.0;   // Eq. (6) diagonal weight
 // Model constants, derived on the host from the caller's parameters.  Constant
 // divisors are stored as reciprocals; u-dependent time constants are divided.
 struct BarkleyC { double b, inv_a, inv_eps; };
+struct FhnC { double eps, a1, a0; };
 struct FentonKarmaC {
   double u_c, u_v, inv_tau_d, inv_tau_0, inv_tau_r, inv_2tau_si, k_si, u_csi,
       tau_v1m, tau_v2m, inv_tau_vp, inv_tau_wm, inv_tau_wp;
@@ -34,6 +35,7 @@ struct BocfC {
 };
 union ModelC {
   BarkleyC bk;
+  FhnC fh;
   FentonKarmaC fk;
   BocfC bo;
   double raw[32];
@@ -49,17 +51,21 @@ struct KConst {
   double k;          // H_k sharpness (+inf for the Heaviside step)
   double k6;         // dH_k/dt scale 6 k (0 for the Heaviside step)
   double dt, h2, h6; // dt, dt/2, dt/6
-  double cD;         // D_par / dx^2 (isotropic stencils)
-  double inv_dx2;    // 1 / dx^2 (anisotropic flux form)
+  // Scale of the diffusion operator of diffusive field d (u, then v for
+  // FitzHugh-Nagumo, whose v diffuses delta times faster): (D_par rel_d) / dx^2
+  // for the isotropic stencils, rel_d / dx^2 for the anisotropic flux form.
+  double dcoef[2];
   double theta0, dtheta, n_total, d_perp, dd;  // fibre field, dd = D_par - D_perp
   ModelC m;
 };
 
+// NV fields per cell; the first NDIFF of them diffuse.
 template <int MODEL> struct ModelTraits;
-template <> struct ModelTraits<RD_MODEL_DIFFUSION> { static constexpr int NV = 1; };
-template <> struct ModelTraits<RD_MODEL_BARKLEY> { static constexpr int NV = 2; };
-template <> struct ModelTraits<RD_MODEL_FENTON_KARMA> { static constexpr int NV = 3; };
-template <> struct ModelTraits<RD_MODEL_BOCF> { static constexpr int NV = 4; };
+template <> struct ModelTraits<RD_MODEL_DIFFUSION> { static constexpr int NV = 1, NDIFF = 1; };
+template <> struct ModelTraits<RD_MODEL_BARKLEY> { static constexpr int NV = 2, NDIFF = 1; };
+template <> struct ModelTraits<RD_MODEL_FENTON_KARMA> { static constexpr int NV = 3, NDIFF = 1; };
+template <> struct ModelTraits<RD_MODEL_BOCF> { static constexpr int NV = 4, NDIFF = 1; };
+template <> struct ModelTraits<RD_MODEL_FHN> { static constexpr int NV = 2, NDIFF = 2; };
 
 // ---------------------------------------------------------------------------
 // Smoothed step: t = kx + 1/2 clamped to [0, 1], H = t^2 (3 - 2t).  Clamping
@@ -224,6 +230,19 @@ template <> struct Reaction<RD_MODEL_BARKLEY> {
   }
 };
 
+// FitzHugh-Nagumo, Eq. (3) without its diffusion terms:
+// du = u - v - u^3, dv = eps (u - a1 v - a0).  Rounded as written (matches the
+// oracle bit for bit).
+template <> struct Reaction<RD_MODEL_FHN> {
+  template <class T>
+  __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
+    const FhnC& m = c.m.fh;
+    const T u = y[0], v = y[1];
+    f[0] = (u - v) - (u * u) * u;
+    f[1] = m.eps * ((u - m.a1 * v) - m.a0);
+  }
+};
+
 // Fenton-Karma three-variable model, gates through H_k:
 // J_fi = -v p (1-u)(u-u_c)/tau_d, J_so = u(1-p)/tau_0 + p/tau_r,
 // J_si = -w (1 + tanh(k_si (u - u_csi))) / (2 tau_si),
@@ -379,12 +398,12 @@ __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool anis
 // YEDGE = false promises 0 < rho < ny - 1 (no boundary face in y).
 template <int STENCIL, bool EDGE, bool YEDGE = true>
 __device__ __forceinline__ double diffusion(double up, double cen, double dn, const Column& col,
-                                            int rho, const KConst& c) {
+                                            int rho, const KConst& c, double coef) {
   if constexpr (STENCIL == RD_LAP5) {
     double w = from_west(cen), e = from_east(cen);
     if (EDGE && col.west) w = cen;
     if (EDGE && col.east) e = cen;
-    return c.cD * (((w + e) + (up + dn)) - 4.0 * cen);
+    return coef * (((w + e) + (up + dn)) - 4.0 * cen);
   } else if constexpr (STENCIL == RD_LAP9) {
     const double cs = up + dn;  // N + S of this column
     double w = from_west(cen), e = from_east(cen);
@@ -393,7 +412,7 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
     if (EDGE && col.east) { e = cen; es = cs; }
     const double axial = ((w + e) + cs) - 4.0 * cen;
     const double diag = (ws + es) - 4.0 * cen;
-    return c.cD * (kAlphaAxial * axial + kAlphaDiag * diag);
+    return coef * (kAlphaAxial * axial + kAlphaDiag * diag);
   } else {
     // Conservative flux form: x-face fluxes shared with the west neighbour
     // through a lane shuffle, y-face fluxes recomputed by both rows with the
@@ -413,7 +432,7 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
     double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (cen - up);
     if (YEDGE && rho == c.ny - 1) fys = 0.0;
     if (YEDGE && rho == 0) fyn = 0.0;
-    return ((fxe - fxw) + (fys - fyn)) * c.inv_dx2;
+    return ((fxe - fxw) + (fys - fyn)) * coef;
   }
 }
 
@@ -427,16 +446,16 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
 template <int STENCIL, bool EDGE>
 __device__ __forceinline__ double diffusion_rows(const double* up, const double* cen, const double* dn,
                                                  int il, int iw, int ie, const Column& col, int rho,
-                                                 const KConst& c) {
+                                                 const KConst& c, double coef) {
   const double C = cen[il];
   if constexpr (STENCIL == RD_LAP5) {
-    return c.cD * (((cen[iw] + cen[ie]) + (up[il] + dn[il])) - 4.0 * C);
+    return coef * (((cen[iw] + cen[ie]) + (up[il] + dn[il])) - 4.0 * C);
   } else if constexpr (STENCIL == RD_LAP9) {
     const double cs = up[il] + dn[il];
     const double ws = up[iw] + dn[iw], es = up[ie] + dn[ie];
     const double axial = ((cen[iw] + cen[ie]) + cs) - 4.0 * C;
     const double diag = (ws + es) - 4.0 * C;
-    return c.cD * (kAlphaAxial * axial + kAlphaDiag * diag);
+    return coef * (kAlphaAxial * axial + kAlphaDiag * diag);
   } else {
     const double u = up[il], d = dn[il];
     double fxe = col.dxx_e * (cen[il + 1] - C) + col.dxy_e4 * ((dn[il + 1] + d) - (up[il + 1] + u));
@@ -448,7 +467,7 @@ __device__ __forceinline__ double diffusion_rows(const double* up, const double*
     double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (C - u);
     if (rho == c.ny - 1) fys = 0.0;
     if (rho == 0) fyn = 0.0;
-    return ((fxe - fxw) + (fys - fyn)) * c.inv_dx2;
+    return ((fxe - fxw) + (fys - fyn)) * coef;
   }
 }
 

@@ -35,8 +35,9 @@ constexpr int kPad = kWave + 2;  // LDS row: 64 lanes and a pad column on each s
 
 template <int MODEL, int NS, int MODE> struct PipeShape {
   static constexpr int NV = ModelTraits<MODEL>::NV;
+  static constexpr int NDF = ModelTraits<MODEL>::NDIFF;
   static constexpr int NF = (MODE == kModeTangent ? 2 : 1) * NV;
-  static constexpr int ND = MODE == kModeTangent ? 2 : 1;
+  static constexpr int ND = (MODE == kModeTangent ? 2 : 1) * NDF;
   static constexpr int NG = NF - ND;
   static constexpr int NI = NS > 1 ? NS - 1 : 1;  // stages fed through G and A
   static constexpr int U_doubles = NS * 4 * ND * kPad;
@@ -50,13 +51,15 @@ __device__ __forceinline__ void pipe_block_impl(const double* const* in, double*
                                                 double* const (*ys)[kMaxFields], const KConst& c,
                                                 int blk, double* lds) {
   using Sh = PipeShape<MODEL, NS, MODE>;
-  constexpr int NV = Sh::NV, NF = Sh::NF, ND = Sh::ND, NG = Sh::NG;
+  constexpr int NV = Sh::NV, NDF = Sh::NDF, NF = Sh::NF, ND = Sh::ND, NG = Sh::NG;
   constexpr bool TAN = MODE == kModeTangent;
   constexpr bool STAGES = MODE == kModeStages;
   constexpr int TX = kWave - 2 * NS;
-  auto comp = [](int d) { return d == 0 ? 0 : NV; };
-  auto diffusive = [](int f) { return f == 0 || (TAN && f == NV); };
-  auto gidx = [](int f) { return f < NV ? f - 1 : f - 2; };  // index among non-diffusive fields
+  // packed index of diffusive component d, whether packed value f diffuses,
+  // and the index of a non-diffusive value among the non-diffusive ones
+  auto comp = [](int d) { return d < NDF ? d : NV + (d - NDF); };
+  auto diffusive = [](int f) { return f < NDF || (TAN && f >= NV && f - NV < NDF); };
+  auto gidx = [](int f) { return f < NV ? f - NDF : (NV - NDF) + (f - NV - NDF); };
 
   const int lane = threadIdx.x & (kWave - 1);
   const int s = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) + 1;  // this wave's stage
@@ -143,7 +146,7 @@ __device__ __forceinline__ void pipe_block_impl(const double* const* in, double*
 #pragma unroll
       for (int d = 0; d < ND; ++d)
         lap[d] = diffusion_rows<STENCIL, EDGE>(urow(s, ru, d), urow(s, rho, d), urow(s, rd, d), il, iw, ie,
-                                               col, rho, c);
+                                               col, rho, c, c.dcoef[d % NDF]);
       double k[NF];
       eval_rates<MODEL, TAN>(c, y, k);
 #pragma unroll

@@ -1,0 +1,8 @@
+// Stage-pipelined fused-step kernels of the FitzHugh-Nagumo model advancing the state and a tangent, all stencils and schemes.
+#include "rd_pipe.h"
+
+namespace rd {
+hipError_t launch_pipe_tan_fhn(int stencil, int scheme, const SweepArgs& a, hipStream_t stream) {
+  return launch_pipe_model<RD_MODEL_FHN, kModeTangent>(stencil, scheme, a, stream);
+}
+}  // namespace rd

@@ -64,7 +64,9 @@ template <> struct Scheme<4> {
 // reads and writes the state once for several steps.  1 elsewhere.
 template <int MODEL, int NS, int MODE> struct MultiStep {
   static constexpr int max =
-      MODE == kModeStep && (MODEL == RD_MODEL_DIFFUSION || MODEL == RD_MODEL_BARKLEY) ? 8 / NS : 1;
+      MODE == kModeStep && (MODEL == RD_MODEL_DIFFUSION || MODEL == RD_MODEL_BARKLEY || MODEL == RD_MODEL_FHN)
+          ? 8 / NS
+          : 1;
 };
 
 // Waves per SIMD each kernel's register budget is sized for (the largest
@@ -112,13 +114,15 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   constexpr bool TAN = MODE == kModeTangent;
   constexpr bool STAGES = MODE == kModeStages;
   constexpr int NV = ModelTraits<MODEL>::NV;
-  constexpr int NF = TAN ? 2 * NV : NV;  // values per cell carried
-  constexpr int ND = TAN ? 2 : 1;        // diffusive components: u (and du)
-  constexpr int KS = K * NS;             // stages per launch
+  constexpr int NDF = ModelTraits<MODEL>::NDIFF;  // diffusive fields: 0 .. NDF-1
+  constexpr int NF = TAN ? 2 * NV : NV;           // values per cell carried
+  constexpr int ND = TAN ? 2 * NDF : NDF;         // diffusive components (and their tangents)
+  constexpr int KS = K * NS;                      // stages per launch
   constexpr int TX = kWave - 2 * KS;
   constexpr int ZR = (NS + 1 > 3) ? NS + 1 : 3;
-  auto comp = [](int d) { return d == 0 ? 0 : NV; };  // index of diffusive component d
-  auto diffusive = [](int f) { return f == 0 || (TAN && f == NV); };
+  // packed index of diffusive component d, and whether packed value f diffuses
+  auto comp = [](int d) { return d < NDF ? d : NV + (d - NDF); };
+  auto diffusive = [](int f) { return f < NDF || (TAN && f >= NV && f - NV < NDF); };
 
   const int lane = threadIdx.x & (kWave - 1);
   const int sx = wid / c.nby;  // bands of one strip are consecutive
@@ -279,7 +283,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         double lap[ND];
 #pragma unroll
         for (int d = 0; d < ND; ++d)
-          lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c);
+          lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c, c.dcoef[d % NDF]);
         double kr[NF];
         eval_rates<MODEL, TAN>(c, y, kr);
 #pragma unroll
@@ -316,9 +320,8 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
           for (int d = 0; d < ND; ++d) yu[k][s + 1][0][d] = zr[k][s][comp(d)] + cs * kr[comp(d)];
           if (STAGES && out_col && rho >= yA && rho < yB) {
             const size_t o = (size_t)rho * nx + gx;
-            ys[s - 1][0][o] = yu[k][s + 1][0][0];
 #pragma unroll
-            for (int f = 1; f < NV; ++f) ys[s - 1][f][o] = ygn[k][s + 1][f];
+            for (int f = 0; f < NV; ++f) ys[s - 1][f][o] = f < NDF ? yu[k][s + 1][0][f] : ygn[k][s + 1][f];
           }
         } else if (!STAGES) {
           const double bw = NS == 4 ? c.h6 : c.h2;
@@ -436,14 +439,17 @@ RD_DECLARE_SWEEP(fwd, diffusion)
 RD_DECLARE_SWEEP(fwd, barkley)
 RD_DECLARE_SWEEP(fwd, fk)
 RD_DECLARE_SWEEP(fwd, bocf)
+RD_DECLARE_SWEEP(fwd, fhn)
 RD_DECLARE_SWEEP(tan, diffusion)
 RD_DECLARE_SWEEP(tan, barkley)
 RD_DECLARE_SWEEP(tan, fk)
 RD_DECLARE_SWEEP(tan, bocf)
+RD_DECLARE_SWEEP(tan, fhn)
 RD_DECLARE_SWEEP(stg, diffusion)
 RD_DECLARE_SWEEP(stg, barkley)
 RD_DECLARE_SWEEP(stg, fk)
 RD_DECLARE_SWEEP(stg, bocf)
+RD_DECLARE_SWEEP(stg, fhn)
 #undef RD_DECLARE_SWEEP
 #define RD_DECLARE_PIPE(kind, model) \
   hipError_t launch_pipe_##kind##_##model(int stencil, int scheme, const SweepArgs& a, hipStream_t s);
@@ -451,14 +457,17 @@ RD_DECLARE_PIPE(fwd, diffusion)
 RD_DECLARE_PIPE(fwd, barkley)
 RD_DECLARE_PIPE(fwd, fk)
 RD_DECLARE_PIPE(fwd, bocf)
+RD_DECLARE_PIPE(fwd, fhn)
 RD_DECLARE_PIPE(tan, diffusion)
 RD_DECLARE_PIPE(tan, barkley)
 RD_DECLARE_PIPE(tan, fk)
 RD_DECLARE_PIPE(tan, bocf)
+RD_DECLARE_PIPE(tan, fhn)
 RD_DECLARE_PIPE(stg, diffusion)
 RD_DECLARE_PIPE(stg, barkley)
 RD_DECLARE_PIPE(stg, fk)
 RD_DECLARE_PIPE(stg, bocf)
+RD_DECLARE_PIPE(stg, fhn)
 #undef RD_DECLARE_PIPE
 
 // Kernel variants of the fused step (identical results): one wave carrying

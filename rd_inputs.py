@@ -30,6 +30,11 @@ import numpy as np
 BARKLEY_PARAM_NAMES = ("a", "b", "eps")
 BARKLEY_PARAMS = {"a": 0.75, "b": 0.02, "eps": 0.02}
 
+# FitzHugh-Nagumo, Eq. (3), with the nondimensional values of Sect. 2:
+# (delta, eps, a1, a0) = (1.5, 0.05, 1.5, -0.1), dx = dy = 0.04.
+FHN_PARAM_NAMES = ("delta", "eps", "a1", "a0")
+FHN_PARAMS = {"delta": 1.5, "eps": 0.05, "a1": 1.5, "a0": -0.1}
+
 # Fenton & Karma (1998), parameter set fitted to the Beeler-Reuter model.
 # Times in ms, voltage dimensionless.
 FK_PARAM_NAMES = (
@@ -70,14 +75,16 @@ PARAM_NAMES = {
     "barkley": BARKLEY_PARAM_NAMES,
     "fk": FK_PARAM_NAMES,
     "bocf": BOCF_PARAM_NAMES,
+    "fhn": FHN_PARAM_NAMES,
 }
 DEFAULT_PARAMS = {
     "diffusion": {},
     "barkley": BARKLEY_PARAMS,
     "fk": FK_PARAMS,
     "bocf": BOCF_PARAMS,
+    "fhn": FHN_PARAMS,
 }
-N_FIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4}
+N_FIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4, "fhn": 2}
 
 # Width parameter of the smoothed step function (Sect. 2): k = 28.4.
 STEP_K = 28.4
@@ -125,6 +132,12 @@ _WORKLOADS = {
                                 theta0=-math.pi / 3.0, theta1=math.pi / 3.0,
                                 ic="bocf", seed=3),
     # Barkley 1024x1024 RK4 4000 steps (adjoint workload), checkpoints every 64.
+    # FitzHugh-Nagumo 256x256 (the grid of the convergence study, Sect. 5),
+    # dx = 0.04, 9-point Laplacian on u and v (v with delta D), RK4; dt inside
+    # every scheme's stability limit for both stencils.
+    "fhn_256_rk4": dict(_BASE, model="fhn", stencil="lap9", scheme="rk4",
+                        nx=256, ny=256, dx=0.04, dt=2e-4, nsteps=1000,
+                        D_par=1.0, ic="fhn", seed=6),
     "barkley_1024_rk4_adjoint": dict(_BASE, model="barkley", stencil="lap5", scheme="rk4",
                                      nx=1024, ny=1024, dx=0.5, dt=0.02, nsteps=4000,
                                      D_par=1.0, ic="barkley", seed=5,
@@ -232,6 +245,17 @@ def bocf_ic(nx: int, ny: int, seed: int, amp: float = 1e-4, blocks: int = 4) -> 
     return _noise(rng, [u, v, w, s], amp)
 
 
+def fhn_ic(nx: int, ny: int, seed: int, amp: float = 1e-3) -> list[np.ndarray]:
+    """Cross-field spiral seed for Eq. (3): u = 1 for x < L/2 (else -1),
+    v = 0.5 for y < L/2 (else -0.5), plus noise U[0, amp) on u then v."""
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    u = np.where(i < nx / 2, 1.0, -1.0) * np.ones((ny, 1))
+    v = np.where(j < ny / 2, 0.5, -0.5) * np.ones((1, nx))
+    rng = np.random.default_rng(seed)
+    return _noise(rng, [np.ascontiguousarray(u), np.ascontiguousarray(v)], amp)
+
+
 def diffusion_ic(nx: int, ny: int, seed: int) -> list[np.ndarray]:
     """Random field in [0, 1) for the pure-diffusion test model."""
     rng = np.random.default_rng(seed)
@@ -249,6 +273,8 @@ def initial_condition(w: dict) -> list[np.ndarray]:
         return bocf_ic(w["nx"], w["ny"], w["seed"])
     if kind == "diffusion":
         return diffusion_ic(w["nx"], w["ny"], w["seed"])
+    if kind == "fhn":
+        return fhn_ic(w["nx"], w["ny"], w["seed"])
     raise ValueError(f"unknown initial condition {kind!r}")
 
 
@@ -256,6 +282,8 @@ def random_fields(model: str, nx: int, ny: int, seed: int) -> list[np.ndarray]:
     """Random state inside the physiological range of ``model`` (tests)."""
     rng = np.random.default_rng(seed)
     nv = N_FIELDS[model]
+    if model == "fhn":  # u in (-1.2, 1.2), v in (-0.6, 0.6)
+        return [(rng.random((ny, nx)) - 0.5) * 2.4, (rng.random((ny, nx)) - 0.5) * 1.2]
     hi = {"diffusion": 1.0, "barkley": 1.0, "fk": 1.0, "bocf": 1.55}[model]
     u = rng.random((ny, nx)) * hi
     return [u] + [rng.random((ny, nx)) for _ in range(nv - 1)]

@@ -121,3 +121,13 @@ def test_steps_per_launch_knob():
         assert rd.get_steps_per_launch(pb) == 1       # untuned start
     finally:
         rd.set_steps_per_launch(None)
+
+
+def test_fhn_model_tables_and_negative_delta_rejected():
+    assert rd.n_fields("fhn") == 2 and rd.n_params("fhn") == 4
+    w = ri.workload("fhn_256_rk4", nx=32, ny=24)
+    p = rd.Problem.from_workload(w, ri.params_array("fhn", {"delta": -0.5}))
+    cp, _buf = p.to_c()
+    out = C.c_size_t(0)
+    assert B.lib().rd_workspace_bytes(C.byref(cp), 0, C.byref(out)) == -1
+    assert "delta" in B.lib().rd_last_error().decode()

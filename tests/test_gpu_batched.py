@@ -16,6 +16,7 @@ SIZES = [(40, 40), (64, 64), (97, 61), (130, 70), (1, 5), (57, 1), (200, 33)]
 
 def batch_setup(model, stencil, scheme, steps, sizes=SIZES, seed=0):
     base = {"barkley": "barkley_1024_rk4_adjoint", "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4",
+            "fhn": "fhn_256_rk4",
             "diffusion": "bocf_2048_aniso_rk4"}[model]
     out = []
     for k, (nx, ny) in enumerate(sizes):
@@ -28,6 +29,7 @@ def batch_setup(model, stencil, scheme, steps, sizes=SIZES, seed=0):
 
 
 @pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rk4"), ("barkley", "lap5", "euler"),
+                                                  ("fhn", "lap9_aniso", "rk4"),
                                                   ("bocf", "lap9_aniso", "heun"), ("diffusion", "lap9", "rk4")])
 @pytest.mark.parametrize("steps", [1, 6])
 @pytest.mark.parametrize("tangent", [False, True])

@@ -15,8 +15,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-11  # relative L-infinity, per field
 BASE = {"diffusion": "bocf_2048_aniso_rk4", "barkley": "barkley_128_euler",
-        "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4"}
-COMBOS = list(itertools.product(["diffusion", "barkley", "fk", "bocf"],
+        "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4", "fhn": "fhn_256_rk4"}
+COMBOS = list(itertools.product(["diffusion", "barkley", "fk", "bocf", "fhn"],
                                 ["lap5", "lap9", "lap9_aniso"], ["euler", "heun", "rk4"]))
 
 
@@ -53,7 +53,7 @@ def test_every_combination_matches_oracle(model, stencil, scheme, variant):
     err = rel_linf(got, ref)
     print(f"{variant} {model} {stencil} {scheme}: rel-Linf {err:.3e}")
     assert err <= TOL
-    if model in ("diffusion", "barkley") and stencil != "lap9_aniso":
+    if model in ("diffusion", "barkley", "fhn") and stencil != "lap9_aniso":
         # same operations in the same order, no library math: bit-identical
         assert all(np.array_equal(g, r) for g, r in zip(got, ref))
 
@@ -80,6 +80,7 @@ def test_kernel_variants_and_band_heights_agree_bitwise(model, stencil, scheme):
 
 @pytest.mark.parametrize("model,stencil,scheme", [("barkley", "lap5", "euler"), ("barkley", "lap9", "heun"),
                                                   ("barkley", "lap5", "rk4"), ("diffusion", "lap9_aniso", "euler"),
+                                                  ("fhn", "lap9", "euler"), ("fhn", "lap9_aniso", "heun"),
                                                   ("diffusion", "lap9", "rk4")])
 @pytest.mark.parametrize("nx,ny", [(150, 77), (5, 3), (49, 200)])
 def test_steps_per_launch_agree_bitwise(model, stencil, scheme, nx, ny):
@@ -125,6 +126,7 @@ def test_barkley_euler_eight_steps_per_launch_matches_oracle_bitwise():
     ("fk_1024_rk4", "fk", (160, 120), 1000),
     ("bocf_2048_aniso_rk4", "bocf", (128, 96), 1000),
     ("barkley_1024_rk4_adjoint", "barkley", (200, 136), 1000),
+    ("fhn_256_rk4", "fhn", (192, 160), 1000),
 ])
 def test_thousand_steps_match_oracle(name, model, n, steps):
     w = ri.workload(name) if n is None else ri.workload(name, nx=n[0], ny=n[1])
@@ -241,3 +243,30 @@ def test_pure_diffusion_conserves_on_gpu():
     z0 = ri.diffusion_ic(300, 200, 4)
     got = gpu_step(pr, z0)[0]
     assert abs(got.sum() - z0[0].sum()) <= 1e-13 * z0[0].sum()
+
+
+def _gpu_orders(workload, model, stencil, scheme, n, T, dt0, levels):
+    w = ri.workload(workload, model=model, stencil=stencil, scheme=scheme, nx=n, ny=n)
+    z0 = ri.initial_condition(w)
+    sols = []
+    for lv in range(levels):
+        dt = dt0 / 2 ** lv
+        _, pr = problems(dict(w, dt=dt), nsteps=int(round(T / dt)))
+        sols.append(np.concatenate([a.ravel() for a in gpu_step(pr, z0)]))
+    e = [np.linalg.norm(sols[k] - sols[k + 1]) / np.linalg.norm(sols[k + 1]) for k in range(levels - 1)]
+    return [math.log2(e[k] / e[k + 1]) for k in range(len(e) - 1)]
+
+
+@pytest.mark.parametrize("scheme,expected", [("euler", 1), ("heun", 2), ("rk4", 4)])
+def test_fhn_convergence_orders_on_gpu(scheme, expected):
+    """Table 1, FitzHugh-Nagumo column (theoretical orders), measured on the
+    GPU path by Richardson differences at the paper's dx = 0.04."""
+    orders = _gpu_orders("fhn_256_rk4", "fhn", "lap9", scheme, 48, 0.06, 3e-4, 5)
+    assert abs(orders[-1] - expected) < 0.15, orders
+
+
+@pytest.mark.parametrize("scheme,expected", [("euler", 1), ("heun", 2), ("rk4", 3)])
+def test_bocf_convergence_orders_on_gpu(scheme, expected):
+    """Table 1, Bueno-Orovio column: RK4 shows order 3 with the C1 step H_k."""
+    orders = _gpu_orders("bocf_2048_aniso_rk4", "bocf", "lap9_aniso", scheme, 24, 8.0, 0.05, 5)
+    assert abs(orders[-1] - expected) < 0.2, orders

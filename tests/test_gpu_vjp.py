@@ -15,8 +15,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
 BASE = {"diffusion": "barkley_1024_rk4_adjoint", "barkley": "barkley_1024_rk4_adjoint",
-        "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4"}
-CASES = [(m, st, sc) for m in ("barkley", "fk", "bocf", "diffusion")
+        "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4", "fhn": "fhn_256_rk4"}
+CASES = [(m, st, sc) for m in ("barkley", "fk", "bocf", "diffusion", "fhn")
          for st in ("lap5", "lap9") for sc in ("euler", "heun", "rk4")]
 
 

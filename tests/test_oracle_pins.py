@@ -129,6 +129,55 @@ def test_pure_diffusion_mode_decay(stencil, scheme, R):
     assert np.max(np.abs(out - expect)) <= 1e-13 * np.max(np.abs(expect))
 
 
+@pytest.mark.parametrize("stencil", ["lap5", "lap9"])
+@pytest.mark.parametrize("scheme,R", [
+    ("euler", lambda x: 1 + x),
+    ("heun", lambda x: 1 + x + x * x / 2),
+    ("rk4", lambda x: 1 + x + x * x / 2 + x ** 3 / 6 + x ** 4 / 24),
+])
+def test_fhn_second_field_diffuses_with_delta(stencil, scheme, R):
+    """Eq. (3) with eps = 0 leaves v alone with delta lap v: a DCT mode of v
+    decays as R(delta lambda dt)^n, whatever u does (pins v's diffusivity)."""
+    nx, ny, dx, dt, steps, delta = 12, 9, 0.5, 0.01, 40, 1.5
+    phi = dct_mode(nx, ny, 2, 3)
+    p = prob(model="fhn", stencil=stencil, scheme=scheme, nx=nx, ny=ny, dx=dx, dt=dt,
+             params=(delta, 0.0, 1.5, -0.1))
+    lam = dct_eigenvalue(stencil, delta / dx ** 2, nx, ny, 2, 3)
+    u0 = 0.3 * np.cos(np.arange(nx)[None, :] * 0.7) * np.ones((ny, 1))
+    out = oracle.step(p, [u0, phi], steps)[1]
+    expect = R(lam * dt) ** steps * phi
+    assert np.max(np.abs(out - expect)) <= 1e-13 * np.max(np.abs(expect))
+
+
+def test_fhn_brute_force_euler_step():
+    """Eq. (3), one explicit Euler step with the 5-point stencil and mirrored
+    ghosts written as scalar loops on a 5 x 4 grid: the oracle's step agrees
+    bit for bit."""
+    nx, ny, dx, dt = 5, 4, 0.3, 0.001
+    delta, eps, a1, a0 = 1.5, 0.05, 1.5, -0.1
+    rng = np.random.default_rng(7)
+    u = (rng.random((ny, nx)) - 0.5) * 2.0
+    v = (rng.random((ny, nx)) - 0.5)
+    c_u, c_v = 1.0 / (dx * dx), (1.0 * delta) / (dx * dx)
+
+    def at(a, j, i):
+        return a[min(max(j, 0), ny - 1)][min(max(i, 0), nx - 1)]
+
+    un, vn = np.empty_like(u), np.empty_like(v)
+    for j in range(ny):
+        for i in range(nx):
+            lu = c_u * (((at(u, j, i - 1) + at(u, j, i + 1)) + (at(u, j - 1, i) + at(u, j + 1, i))) - 4.0 * u[j, i])
+            lv = c_v * (((at(v, j, i - 1) + at(v, j, i + 1)) + (at(v, j - 1, i) + at(v, j + 1, i))) - 4.0 * v[j, i])
+            fu = (u[j, i] - v[j, i]) - (u[j, i] * u[j, i]) * u[j, i]
+            fv = eps * ((u[j, i] - a1 * v[j, i]) - a0)
+            un[j, i] = u[j, i] + dt * (lu + fu)
+            vn[j, i] = v[j, i] + dt * (lv + fv)
+    p = prob(model="fhn", stencil="lap5", scheme="euler", nx=nx, ny=ny, dx=dx, dt=dt,
+             params=(delta, eps, a1, a0))
+    out = oracle.step(p, [u, v], 1)
+    assert np.array_equal(out[0], un) and np.array_equal(out[1], vn)
+
+
 @pytest.mark.parametrize("stencil", ["lap5", "lap9", "lap9_aniso"])
 @pytest.mark.parametrize("scheme", ["euler", "rk4"])
 def test_pure_diffusion_conserves_sum(stencil, scheme):
@@ -325,6 +374,7 @@ def test_bocf_matches_textbook_away_from_thresholds(u):
     ("barkley", (0.8, 0.1), 1.0, 0.005),
     ("fk", (0.3, 1.0, 1.0), 10.0, 0.01),
     ("bocf", (0.5, 1.0, 1.0, 0.0), 10.0, 0.01),
+    ("fhn", (0.7, -0.2), 5.0, 0.005),
 ])
 def test_uniform_state_follows_the_ode(model, z0, T, dt):
     """A spatially uniform state stays exactly uniform and follows the local
@@ -345,7 +395,8 @@ def test_uniform_state_follows_the_ode(model, z0, T, dt):
 
 
 def richardson_orders(model, stencil, scheme, n, T, dt0, levels, step_k=ri.STEP_K):
-    base = {"barkley": "barkley_128_euler", "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4"}[model]
+    base = {"barkley": "barkley_128_euler", "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4",
+            "fhn": "fhn_256_rk4"}[model]
     w = ri.workload(base, nx=n, ny=n, stencil=stencil, scheme=scheme)
     z0 = ri.initial_condition(w)
     sols = []
@@ -362,6 +413,15 @@ def richardson_orders(model, stencil, scheme, n, T, dt0, levels, step_k=ri.STEP_
 def table1():
     with open(os.path.join(GOLDEN, "table1_orders.json")) as fh:
         return json.load(fh)
+
+
+@pytest.mark.parametrize("scheme,key", [("euler", "explicit_euler"), ("heun", "heun"), ("rk4", "rk4")])
+def test_fhn_orders_match_table1(scheme, key):
+    """FitzHugh-Nagumo (Eq. 3) with the paper's dx = 0.04: Table 1 reports
+    the theoretical orders 1, 2 and 4."""
+    expected = table1()["observed"][key][0]
+    orders = richardson_orders("fhn", "lap9", scheme, 32, 0.06, 3e-4, 5)
+    assert abs(orders[-1] - expected) < 0.15, orders
 
 
 @pytest.mark.parametrize("scheme,key", [("euler", "explicit_euler"), ("heun", "heun"), ("rk4", "rk4")])
@@ -394,13 +454,13 @@ def test_sharp_heaviside_drops_rk4_to_first_order():
 CASES = [
     ("barkley", "lap5", "rk4"), ("barkley", "lap5", "euler"), ("fk", "lap9", "rk4"),
     ("fk", "lap9", "heun"), ("bocf", "lap9_aniso", "rk4"), ("bocf", "lap9", "euler"),
-    ("diffusion", "lap9_aniso", "rk4"),
+    ("diffusion", "lap9_aniso", "rk4"), ("fhn", "lap9", "rk4"), ("fhn", "lap5", "heun"),
 ]
 
 
 def case_problem(model, stencil, scheme, nx=14, ny=11):
     base = {"barkley": "barkley_1024_rk4_adjoint", "fk": "fk_1024_rk4",
-            "bocf": "bocf_2048_aniso_rk4", "diffusion": "bocf_2048_aniso_rk4"}[model]
+            "bocf": "bocf_2048_aniso_rk4", "diffusion": "bocf_2048_aniso_rk4", "fhn": "fhn_256_rk4"}[model]
     w = ri.workload(base, nx=nx, ny=ny, model=model, stencil=stencil, scheme=scheme)
     if model == "diffusion":
         w["ic"] = "diffusion"
@@ -439,7 +499,8 @@ def test_dot_product_jvp_vjp(model, stencil, scheme):
 
 
 @pytest.mark.parametrize("model,stencil,scheme", [("barkley", "lap9", "rk4"), ("fk", "lap5", "heun"),
-                                                  ("bocf", "lap9_aniso", "rk4")])
+                                                  ("bocf", "lap9_aniso", "rk4"), ("fhn", "lap9", "rk4"),
+                                                  ("fhn", "lap9_aniso", "euler")])
 def test_vjp_equals_transpose_of_dense_jacobian(model, stencil, scheme):
     p, z0 = case_problem(model, stencil, scheme, nx=4, ny=3)
     nv, n = len(z0), 12
@@ -536,3 +597,5 @@ def test_inputs_are_seeded_and_in_range():
     assert abs(sum(float(np.sum(x * x)) for x in d) - 1.0) < 1e-14
     s = ri.bocf_ic(64, 64, 3)
     assert len(s) == 4 and s[0].max() <= 1.0 + 1e-4
+    f = ri.fhn_ic(40, 30, 6)
+    assert np.array_equal(f[0], ri.fhn_ic(40, 30, 6)[0]) and f[0].max() <= 1.0 + 1e-3 and f[1].min() >= -0.5
