@@ -149,6 +149,20 @@ def other_workloads(rd, torch, dev):
                                      "us_per_step": sec / w["nsteps"] * 1e6,
                                      "hbm_frac": 32 * 128 * 128 * w["nsteps"] / sec / HBM_PEAK}
 
+    # FitzHugh-Nagumo 256^2 (Eq. 3, u and v diffusive), 9-point, RK4, 1000 steps
+    w = ri.workload("fhn_256_rk4")
+    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    p = rd.Problem.from_workload(w, ri.params_array("fhn"), nsteps=8)
+    rd.step(p, z)
+    p.nsteps = w["nsteps"]
+    sec = _timed(torch, stream, lambda: rd.step(p, z))
+    cells = w["nx"] * w["ny"]
+    out["fhn_256_rk4_1000"] = {"seconds": sec, "rate": cells * w["nsteps"] / sec,
+                               "us_per_step": sec / w["nsteps"] * 1e6,
+                               "steps_per_launch": rd.get_steps_per_launch(p),
+                               "plan": list(rd.get_plan(p, "step")),
+                               "hbm_frac": 32 * cells * w["nsteps"] / sec / HBM_PEAK}
+
     # Bueno-Orovio 2048^2, anisotropic flux form, RK4 (50 of its 5000 steps)
     w = ri.workload("bocf_2048_aniso_rk4")
     z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
