@@ -229,6 +229,33 @@ def other_workloads(rd, torch, dev):
                                  "rate_jvp_graph_replay": cells * n / sec_g,
                                  "hbm_frac_jvp": 96 * cells * n / sec_b / HBM_PEAK}
 
+    # Newton-Krylov fixed points of the 200-step FitzHugh-Nagumo flow for a
+    # small ensemble (stable and unstable uniform states), exact vs FD JVPs
+    import numpy as np
+    from paper_1309_1720_amd import krylov
+    fp = ri.FHN_PARAMS
+    roots = sorted(r.real for r in np.roots([1.0, 0.0, -(1.0 - 1.0 / fp["a1"]), -fp["a0"] / fp["a1"]])
+                   if abs(r.imag) < 1e-12)
+    members = []
+    for (nx, ny), u in (((96, 80), roots[0]), ((128, 96), roots[2]), ((160, 128), roots[0])):
+        wk = ri.workload("fhn_256_rk4", nx=nx, ny=ny, nsteps=200)
+        i = np.arange(nx)[None, :]
+        j = np.arange(ny)[:, None]
+        pat = np.cos(np.pi * (i + 0.5) / nx) * np.cos(2 * np.pi * (j + 0.5) / ny)
+        v = (u - fp["a0"]) / fp["a1"]
+        members.append((rd.Problem.from_workload(wk, ri.params_array("fhn")),
+                        [torch.from_numpy(u + 0.01 * pat).to(dev), torch.from_numpy(v + 0.02 * pat).to(dev)]))
+    nk = {}
+    for kind in ("exact", "fd"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = krylov.newton_krylov([m[0] for m in members], [m[1] for m in members], tol=1e-13,
+                                   max_newton=8, jvp=kind)
+        torch.cuda.synchronize()
+        nk[kind] = {"seconds": time.perf_counter() - t0, "residuals": res.residuals,
+                    "krylov_iterations": res.krylov_iterations}
+    out["newton_krylov_fhn_3_members_200_steps"] = nk
+
     # Adjoint: Barkley 1024^2, RK4, 4000 steps, checkpoints every 64
     w = ri.workload("barkley_1024_rk4_adjoint")
     p = rd.Problem.from_workload(w, ri.params_array("barkley"))

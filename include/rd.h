@@ -191,6 +191,27 @@ int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* cons
                     double* const* const* tangents, void* ws, size_t ws_bytes,
                     void* hip_stream);
 
+/*
+ * Krylov vector algebra (an addition to the paper: the matrix-free
+ * Newton-Krylov solves on the time-T flow that Sect. 1 motivates, built on
+ * rd_jvp / rd_step_batched).  A vector is a DEVICE array of n doubles (a
+ * state's fields one after another); `x` is a HOST array of m device
+ * pointers, each to n doubles.  Work is enqueued on `hip_stream`; sums run
+ * in a fixed order (results do not depend on timing).
+ *
+ * rd_vec_gram:    out[k] = sum_i x[k][i] w[i], k < m, 1 <= m <= 64; `out` is
+ *                 a device array of m doubles; workspace (device, 8-byte
+ *                 aligned) of rd_vec_gram_workspace_bytes(m) bytes.
+ * rd_vec_lincomb: y[i] = beta y[i] + sum_k coef[k] x[k][i], 0 <= m <= 64,
+ *                 `coef` a HOST array of m doubles; y is not read when
+ *                 beta == 0; y may be one of the x[k].
+ */
+int rd_vec_gram_workspace_bytes(int32_t m, size_t* out);
+int rd_vec_gram(const double* const* x, int32_t m, const double* w, int64_t n, double* out,
+                void* ws, size_t ws_bytes, void* hip_stream);
+int rd_vec_lincomb(double* y, double beta, const double* const* x, const double* coef, int32_t m,
+                   int64_t n, void* hip_stream);
+
 /* Rows per wavefront band used by later calls from any thread (<= 0:
  * automatic choice).  A performance knob: results do not depend on it. */
 int rd_set_tile_rows(int32_t rows);

@@ -76,6 +76,10 @@ def lib() -> C.CDLL:
             "rd_set_kernel_variant": ([C.c_int32], C.c_int),
             "rd_get_plan": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "rd_set_steps_per_launch": ([C.c_int32], C.c_int),
+            "rd_vec_gram_workspace_bytes": ([C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
+            "rd_vec_gram": ([C.POINTER(_PTR), C.c_int32, _PTR, C.c_int64, _PTR, _PTR, C.c_size_t, _PTR], C.c_int),
+            "rd_vec_lincomb": ([_PTR, C.c_double, C.POINTER(_PTR), C.POINTER(C.c_double), C.c_int32, C.c_int64,
+                                _PTR], C.c_int),
             "rd_get_steps_per_launch": ([P, C.POINTER(C.c_int32)], C.c_int),
             "rd_last_error": ([], C.c_char_p),
         }
@@ -246,6 +250,42 @@ def get_steps_per_launch(prob: Problem) -> int:
     k = C.c_int32(0)
     _check(lib().rd_get_steps_per_launch(C.byref(cp), C.byref(k)))
     return k.value
+
+
+def _vec_check(t, n, what):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"{what}: need a contiguous float64 device tensor of {n} elements")
+
+
+def vec_gram(xs, w: torch.Tensor) -> torch.Tensor:
+    """Device tensor of <x_k, w> for the flat float64 device tensors ``xs``."""
+    n = w.numel()
+    _vec_check(w, n, "w")
+    for x in xs:
+        _vec_check(x, n, "x")
+    m = len(xs)
+    out = torch.empty(m, dtype=torch.float64, device=w.device)
+    need = C.c_size_t(0)
+    _check(lib().rd_vec_gram_workspace_bytes(m, C.byref(need)))
+    ws, wsp = _workspace(need.value, w.device)
+    xp = (_PTR * m)(*[x.data_ptr() for x in xs])
+    _check(lib().rd_vec_gram(xp, m, w.data_ptr(), n, out.data_ptr(), wsp, need.value, _stream(w.device)))
+    return out
+
+
+def vec_lincomb(y: torch.Tensor, beta: float, xs=(), coef=()) -> torch.Tensor:
+    """y <- beta y + sum_k coef[k] xs[k] in place (flat float64 device tensors)."""
+    n = y.numel()
+    _vec_check(y, n, "y")
+    for x in xs:
+        _vec_check(x, n, "x")
+    m = len(xs)
+    if len(coef) != m:
+        raise ValueError("one coefficient per vector")
+    xp = (_PTR * max(m, 1))(*[x.data_ptr() for x in xs])
+    cp = (C.c_double * max(m, 1))(*[float(c) for c in coef])
+    _check(lib().rd_vec_lincomb(y.data_ptr(), float(beta), xp, cp, m, n, _stream(y.device)))
+    return y
 
 
 def set_autotune(enable: bool) -> None:
