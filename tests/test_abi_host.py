@@ -131,3 +131,21 @@ def test_fhn_model_tables_and_negative_delta_rejected():
     out = C.c_size_t(0)
     assert B.lib().rd_workspace_bytes(C.byref(cp), 0, C.byref(out)) == -1
     assert "delta" in B.lib().rd_last_error().decode()
+
+
+def test_krylov_vector_calls_validate_before_launch():
+    L = B.lib()
+    need = C.c_size_t(0)
+    assert L.rd_vec_gram_workspace_bytes(0, C.byref(need)) == -1
+    assert L.rd_vec_gram_workspace_bytes(65, C.byref(need)) == -1
+    assert L.rd_vec_gram_workspace_bytes(3, C.byref(need)) == 0 and need.value >= 3 * 8
+    xs = (C.c_void_p * 3)(0x1000, 0x2000, 0x3000)
+    # too small a workspace, NULL output, bad sizes: rejected on the host
+    assert L.rd_vec_gram(xs, 3, 0x4000, 10, 0x5000, 0x6000, 8, None) == -3
+    assert L.rd_vec_gram(xs, 3, 0x4000, 10, None, 0x6000, need.value, None) == -1
+    assert L.rd_vec_gram(xs, 3, 0x4000, 0, 0x5000, 0x6000, need.value, None) == -1
+    coef = (C.c_double * 3)(1.0, 2.0, 3.0)
+    assert L.rd_vec_lincomb(0x7000, 1.0, xs, coef, -1, 10, None) == -1
+    assert L.rd_vec_lincomb(0x7000, 1.0, xs, coef, 65, 10, None) == -1
+    assert L.rd_vec_lincomb(None, 1.0, xs, coef, 3, 10, None) == -1
+    assert L.rd_vec_lincomb(0x7001, 1.0, xs, coef, 3, 10, None) == -1
