@@ -27,7 +27,7 @@ import bench
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILES = os.path.join(HERE, "profiles")
-KERNEL = "rd::sweep_kernel<2, 9, 4, 0, 1>"
+KERNEL = "rd::sweep_kernel<2, 9, 4, 0, 1, 0>"
 CALIB = "CUDAFunctorOnSelf_add<double>"
 CALIB_BYTES = 1 << 29  # 2^26 doubles read and the same written
 SQ_COUNTERS = ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",

@@ -69,8 +69,22 @@ enum rd_model {
                                 delta, eps, a1, a0                           */
 };
 
-/* Explicit schemes (Sect. 3): Euler (1 stage), Heun (2), classical RK4 (4). */
-enum rd_scheme { RD_SCHEME_EULER = 1, RD_SCHEME_HEUN = 2, RD_SCHEME_RK4 = 4 };
+/* Schemes (Sect. 3): explicit Euler (1 stage), Heun (2), classical RK4 (4);
+ * and the first-order gate schemes the paper applies to the Bueno-Orovio
+ * model (Table 1), for the gated models (Fenton-Karma, Bueno-Orovio) only:
+ * the voltage takes an explicit Euler step and every gate g, whose rate is
+ * alpha g + beta with alpha, beta frozen at z_n, takes
+ *   Rush-Larsen:     g' = g e^{alpha dt} + (beta/alpha)(e^{alpha dt} - 1)
+ *   implicit Euler:  g' = (g + dt beta) / (1 - dt alpha).
+ * rd_step, rd_jvp and rd_step_batched support them; rd_vjp returns
+ * RD_EUNSUPPORTED, as do other models. */
+enum rd_scheme {
+  RD_SCHEME_EULER = 1,
+  RD_SCHEME_HEUN = 2,
+  RD_SCHEME_RK4 = 4,
+  RD_SCHEME_RUSH_LARSEN = 5,
+  RD_SCHEME_IMPLICIT_EULER = 6
+};
 
 /* Diffusion operators.
  *   RD_LAP5       D (W + E + N + S - 4C) / dx^2.

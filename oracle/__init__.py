@@ -17,6 +17,7 @@ Layout (whole-grid NumPy arrays of shape (ny, nx), x fastest):
                      fields), Barkley, Fenton-Karma, Bueno-Orovio (Eq. 5),
                      and pure diffusion (N = 0).
   * ``integrate`` -- explicit Euler, Heun and classical RK4 (Sect. 3), the
+                     Rush-Larsen and implicit-Euler gate steps (Sect. 3), the
                      tangent-linear map by complex-step differentiation of
                      the forward flow, and the adjoint by explicit
                      transposition of each stage.
@@ -28,12 +29,13 @@ function are taken on the real part.
 from .problem import Problem
 from .stencils import (ghost_pad, laplacian, lap5, lap9, lap_aniso, fibre_coefficients,
                        laplacian_matrix)
-from .models import smooth_step, reaction, reaction_jacobian, n_fields, diffusive_fields
+from .models import (smooth_step, reaction, reaction_jacobian, n_fields, diffusive_fields, gate_fields,
+                     gate_coefficients)
 from .integrate import rhs, step, jvp, vjp, step_adjoint, stage_states, transposed_operators
 
 __all__ = [
     "Problem", "ghost_pad", "laplacian", "lap5", "lap9", "lap_aniso",
     "fibre_coefficients", "laplacian_matrix", "smooth_step", "reaction",
-    "reaction_jacobian", "n_fields", "diffusive_fields", "rhs", "step", "jvp", "vjp",
+    "reaction_jacobian", "n_fields", "diffusive_fields", "gate_fields", "gate_coefficients", "rhs", "step", "jvp", "vjp",
     "step_adjoint", "stage_states", "transposed_operators",
 ]

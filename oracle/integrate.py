@@ -13,6 +13,14 @@ with f(z) = (L u + N_u(z), N_h(z)): only the voltage u diffuses, except in
 FitzHugh-Nagumo (Eq. 3), where v diffuses too, with the operator scaled by
 delta.
 
+Rush-Larsen and implicit Euler (Sect. 3; Table 1 applies them to the
+Bueno-Orovio model only, and only to its non-diffusive variables): the
+voltage takes an explicit Euler step; each gate g, whose rate is alpha g +
+beta with alpha, beta frozen at z_n, takes the exponential step
+  g' = g e^{alpha dt} + (beta / alpha)(e^{alpha dt} - 1)        (Rush-Larsen)
+or the implicit Euler step of that linear equation
+  g' = (g + dt beta) / (1 - dt alpha)                           (implicit Euler).
+
 Tangent-linear map: the exact derivative of the discrete flow, obtained by
 running the same forward code in complex arithmetic from z + i h dz and
 reading Im / h (complex-step differentiation; no subtraction, so exact to
@@ -30,7 +38,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .models import diffusive_fields, n_fields, reaction, reaction_jacobian
+from .models import diffusive_fields, gate_coefficients, gate_fields, n_fields, reaction, reaction_jacobian
 from .problem import Problem
 from .stencils import laplacian, laplacian_matrix
 
@@ -55,6 +63,8 @@ def _axpy(z, a, k):
 def _coefficients(prob: Problem):
     """(A, B) of the scheme with the constants exactly as the forward uses them."""
     dt = prob.dt
+    if prob.scheme in ("rush_larsen", "implicit_euler"):
+        raise ValueError(f"{prob.scheme} is not a Runge-Kutta scheme (no stage coefficients)")
     if prob.scheme == "euler":
         return [[]], [dt]
     if prob.scheme == "heun":
@@ -65,8 +75,40 @@ def _coefficients(prob: Problem):
     return [[], [h2], [0.0, h2], [0.0, 0.0, dt]], [h6, 2.0 * h6, 2.0 * h6, h6]
 
 
+def _expm1(x):
+    """e^x - 1; NumPy's expm1 for real input, e^x - 1 for complex input (its
+    imaginary part, which carries the complex-step derivative, suffers no
+    cancellation)."""
+    if np.iscomplexobj(x):
+        return np.exp(x) - 1.0
+    return np.expm1(x)
+
+
+def _gate_step(prob: Problem, z):
+    """One Rush-Larsen or implicit-Euler step (gated models only)."""
+    if not gate_fields(prob):
+        raise ValueError(f"{prob.scheme} needs a gated model (fk, bocf), got {prob.model}")
+    dt = prob.dt
+    k = rhs(prob, z)
+    coef = gate_coefficients(prob, z)
+    out = []
+    for f, zf in enumerate(z):
+        if f in coef:
+            a, b = coef[f]
+            if prob.scheme == "rush_larsen":
+                x = a * dt
+                out.append(zf * np.exp(x) + (b / a) * _expm1(x))
+            else:
+                out.append((zf + dt * b) / (1.0 - dt * a))
+        else:
+            out.append(zf + dt * k[f])
+    return out
+
+
 def _one_step(prob: Problem, z):
     dt = prob.dt
+    if prob.scheme in ("rush_larsen", "implicit_euler"):
+        return _gate_step(prob, z)
     if prob.scheme == "euler":
         k1 = rhs(prob, z)
         return _axpy(z, dt, k1)

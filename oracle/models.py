@@ -179,6 +179,30 @@ def reaction(prob: Problem, z):
     return _bueno_orovio(z, prob.params, prob.step_k)
 
 
+def gate_fields(prob: Problem):
+    """Fields whose rate is linear in the field itself, dg/dt = alpha g + beta
+    with alpha, beta depending on the other fields: the gating variables of
+    the gated models (Fenton-Karma v, w; Bueno-Orovio v, w, s)."""
+    if prob.model in ("fk", "bocf"):
+        return list(range(1, n_fields(prob.model)))
+    return []
+
+
+def gate_coefficients(prob: Problem, z):
+    """{g: (alpha_g, beta_g)} with N_g(z) = alpha_g z_g + beta_g: beta_g is the
+    rate with z_g set to 0 and alpha_g the change of the rate when z_g goes
+    from 0 to 1 (exact for a rate linear in z_g)."""
+    out = {}
+    for g in gate_fields(prob):
+        z0, z1 = list(z), list(z)
+        z0[g] = np.zeros_like(z[g])
+        z1[g] = np.ones_like(z[g])
+        n0 = reaction(prob, z0)[g]
+        n1 = reaction(prob, z1)[g]
+        out[g] = (n1 - n0, n0)
+    return out
+
+
 COMPLEX_STEP = 1e-30
 
 

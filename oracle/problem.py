@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 MODELS = ("diffusion", "barkley", "fk", "bocf", "fhn")
-SCHEMES = ("euler", "heun", "rk4")
+SCHEMES = ("euler", "heun", "rk4", "rush_larsen", "implicit_euler")
 STENCILS = ("lap5", "lap9", "lap9_aniso")
 
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librd.so")
 ABI_VERSION = 1
 
 MODELS = {"diffusion": 0, "barkley": 1, "fk": 2, "bocf": 3, "fhn": 4}
-SCHEMES = {"euler": 1, "heun": 2, "rk4": 4}
+SCHEMES = {"euler": 1, "heun": 2, "rk4": 4, "rush_larsen": 5, "implicit_euler": 6}
 STENCILS = {"lap5": 5, "lap9": 9, "lap9_aniso": 10}
 OPS = {"step": 0, "jvp": 1, "vjp": 2, "batched": 3}
 N_FIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4, "fhn": 2}

@@ -56,9 +56,13 @@ int n_stages(int scheme) {
     case RD_SCHEME_EULER: return 1;
     case RD_SCHEME_HEUN: return 2;
     case RD_SCHEME_RK4: return 4;
+    case RD_SCHEME_RUSH_LARSEN:
+    case RD_SCHEME_IMPLICIT_EULER: return 1;
   }
   return RD_EINVAL;
 }
+
+bool gate_scheme(int scheme) { return scheme == RD_SCHEME_RUSH_LARSEN || scheme == RD_SCHEME_IMPLICIT_EULER; }
 
 static bool finite(double x) { return std::isfinite(x); }
 
@@ -68,6 +72,8 @@ int validate(const rd_problem* p) {
     return fail(RD_EINVAL, "abi_version %u, library has %d", p->abi_version, RD_ABI_VERSION);
   if (n_fields(p->model) < 0) return fail(RD_EINVAL, "unknown model %d", p->model);
   if (n_stages(p->scheme) < 0) return fail(RD_EINVAL, "unknown scheme %d", p->scheme);
+  if (gate_scheme(p->scheme) && p->model != RD_MODEL_FENTON_KARMA && p->model != RD_MODEL_BOCF)
+    return fail(RD_EUNSUPPORTED, "the Rush-Larsen and implicit-Euler schemes need a gated model (Fenton-Karma, Bueno-Orovio)");
   if (p->stencil != RD_LAP5 && p->stencil != RD_LAP9 && p->stencil != RD_LAP9_ANISO)
     return fail(RD_EINVAL, "unknown stencil %d", p->stencil);
   if (p->bc != RD_BC_NOFLUX) return fail(RD_EINVAL, "unknown boundary condition %d", p->bc);
@@ -229,7 +235,7 @@ hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const
       return pipe ? launch_pipe_stg_##name(stencil, scheme, a, s) : launch_sweep_stg_##name(stencil, scheme, a, s); \
   }                                                                                                \
   break;
-  const bool pipe = a.c.variant == kVariantPipe;
+  const bool pipe = a.c.variant == kVariantPipe && !gate_scheme(scheme);  // gate schemes: sweep only
   switch (model) {
     case RD_MODEL_DIFFUSION: RD_MODE_SWITCH(diffusion)
     case RD_MODEL_BARKLEY: RD_MODE_SWITCH(barkley)
@@ -341,7 +347,7 @@ void plan_geometry(const rd_problem* p, KConst& c, bool tangent, double* const* 
     return launch_sweep_mode(tangent ? kModeTangent : kModeStep, p->model, p->stencil, p->scheme, a, s);
   };
   const Plan pl = tuned_plan(tangent ? kTuneTangent : kTuneForward, p->model, p->stencil, p->scheme,
-                             p->nx, p->ny, ns, s, trial, true, 0, 0, kmax);
+                             p->nx, p->ny, ns, s, trial, !gate_scheme(p->scheme), 0, 0, kmax);
   c.variant = pl.variant;
   c.ksteps = pl.k;
   set_geometry(c, ns * pl.k, pl.ty);

@@ -45,6 +45,8 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
   if (rc) return rc;
   if (p->stencil == RD_LAP9_ANISO)
     return fail(RD_EUNSUPPORTED, "rd_vjp supports the 5- and 9-point isotropic stencils");
+  if (gate_scheme(p->scheme))
+    return fail(RD_EUNSUPPORTED, "rd_vjp supports the Euler, Heun and RK4 schemes");
   if (p->checkpoint_every <= 0) return fail(RD_EINVAL, "rd_vjp needs checkpoint_every > 0");
   if (p->nsteps == 0) return RD_OK;
   if (!checkpoints) return fail(RD_EINVAL, "checkpoints is NULL");

@@ -49,7 +49,7 @@ struct BatchCopyArgs {
 __global__ void batch_setup_kernel(BatchSetupArgs a);
 __global__ void batch_copy_kernel(BatchCopyArgs a);
 
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int GATE = 0>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
 void batch_sweep_kernel(BatchArgs a) {
@@ -80,15 +80,19 @@ void batch_sweep_kernel(BatchArgs a) {
     out[f] = a.parity ? I.a[f] : I.b[f];
   }
   double* const no_stages[3][kMaxFields] = {};
-  sweep_wave<MODEL, STENCIL, NS, MODE>(in, out, no_stages, c, wid - I.wave_begin);
+  sweep_wave<MODEL, STENCIL, NS, MODE, 1, GATE>(in, out, no_stages, c, wid - I.wave_begin);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int GATE = 0>
 hipError_t launch_batch(const BatchArgs& a, hipStream_t stream) {
-  const int blocks = (a.total_waves + 3) / 4;
-  hipLaunchKernelGGL((batch_sweep_kernel<MODEL, STENCIL, NS, MODE>), dim3(blocks), dim3(256), 0,
-                     stream, a);
-  return hipGetLastError();
+  if constexpr (GATE != 0 && !ModelTraits<MODEL>::GATED) {
+    return hipErrorInvalidValue;
+  } else {
+    const int blocks = (a.total_waves + 3) / 4;
+    hipLaunchKernelGGL((batch_sweep_kernel<MODEL, STENCIL, NS, MODE, GATE>), dim3(blocks), dim3(256), 0,
+                       stream, a);
+    return hipGetLastError();
+  }
 }
 
 template <int MODEL, int MODE>
@@ -98,16 +102,22 @@ hipError_t launch_batch_model(int stencil, int scheme, const BatchArgs& a, hipSt
       if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP5, 1, MODE>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP5, 2, MODE>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP5, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP5, 1, MODE, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP5, 1, MODE, 2>(a, s);
       break;
     case RD_LAP9:
       if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9, 1, MODE>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9, 2, MODE>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP9, 1, MODE, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP9, 1, MODE, 2>(a, s);
       break;
     case RD_LAP9_ANISO:
       if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9_ANISO, 2, MODE>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9_ANISO, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE, 2>(a, s);
       break;
   }
   return hipErrorInvalidValue;

@@ -59,13 +59,15 @@ struct KConst {
   ModelC m;
 };
 
-// NV fields per cell; the first NDIFF of them diffuse.
+// NV fields per cell; the first NDIFF of them diffuse.  GATED models have
+// gating variables (fields NDIFF .. NV-1) whose rates are affine in the gate
+// itself, dg/dt = alpha g + beta (Reaction<>::gates gives alpha and beta).
 template <int MODEL> struct ModelTraits;
-template <> struct ModelTraits<RD_MODEL_DIFFUSION> { static constexpr int NV = 1, NDIFF = 1; };
-template <> struct ModelTraits<RD_MODEL_BARKLEY> { static constexpr int NV = 2, NDIFF = 1; };
-template <> struct ModelTraits<RD_MODEL_FENTON_KARMA> { static constexpr int NV = 3, NDIFF = 1; };
-template <> struct ModelTraits<RD_MODEL_BOCF> { static constexpr int NV = 4, NDIFF = 1; };
-template <> struct ModelTraits<RD_MODEL_FHN> { static constexpr int NV = 2, NDIFF = 2; };
+template <> struct ModelTraits<RD_MODEL_DIFFUSION> { static constexpr int NV = 1, NDIFF = 1; static constexpr bool GATED = false; };
+template <> struct ModelTraits<RD_MODEL_BARKLEY> { static constexpr int NV = 2, NDIFF = 1; static constexpr bool GATED = false; };
+template <> struct ModelTraits<RD_MODEL_FENTON_KARMA> { static constexpr int NV = 3, NDIFF = 1; static constexpr bool GATED = true; };
+template <> struct ModelTraits<RD_MODEL_BOCF> { static constexpr int NV = 4, NDIFF = 1; static constexpr bool GATED = true; };
+template <> struct ModelTraits<RD_MODEL_FHN> { static constexpr int NV = 2, NDIFF = 2; static constexpr bool GATED = false; };
 
 // ---------------------------------------------------------------------------
 // Smoothed step: t = kx + 1/2 clamped to [0, 1], H = t^2 (3 - 2t).  Clamping
@@ -164,10 +166,38 @@ __device__ __forceinline__ double recip(double d) {
   return r;
 }
 
+// e^x - 1 without the cancellation of exp(x) - 1 near 0: for |x| <= ln2/2
+// the Taylor series x (1 + x/2! + ... + x^13/14!) (truncation < 1e-17
+// relative), elsewhere exp(x) - 1 (no cancellation there).  Both are
+// evaluated and one selected.
+__device__ __forceinline__ double expm1_lean(double x) {
+  double q = 1.0 / 87178291200.0;  // 1/14!
+  q = fma(q, x, 1.0 / 6227020800.0);
+  q = fma(q, x, 1.0 / 479001600.0);
+  q = fma(q, x, 1.0 / 39916800.0);
+  q = fma(q, x, 1.0 / 3628800.0);
+  q = fma(q, x, 1.0 / 362880.0);
+  q = fma(q, x, 1.0 / 40320.0);
+  q = fma(q, x, 1.0 / 5040.0);
+  q = fma(q, x, 1.0 / 720.0);
+  q = fma(q, x, 1.0 / 120.0);
+  q = fma(q, x, 1.0 / 24.0);
+  q = fma(q, x, 1.0 / 6.0);
+  q = fma(q, x, 0.5);
+  q = fma(q, x, 1.0);
+  const double small = x * q;
+  const double large = exp_lean(x) - 1.0;
+  return fabs(x) <= 0.34657359027997264 ? small : large;
+}
+
 __device__ __forceinline__ double exp(double a) { return exp_lean(a); }
+__device__ __forceinline__ double expm1(double a) { return expm1_lean(a); }
 __device__ __forceinline__ Dual exp(Dual a) {
   const double e = exp_lean(a.v);
   return Dual(e, e * a.d);
+}
+__device__ __forceinline__ Dual expm1(Dual a) {
+  return Dual(expm1_lean(a.v), exp_lean(a.v) * a.d);
 }
 __device__ __forceinline__ Dual recip(Dual a) {
   const double r = recip(a.v);
@@ -263,11 +293,51 @@ template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
     f[1] = mad(-(p * v), m.inv_tau_vp, (one_p * (1.0 - v)) * recip(tau_vm));
     f[2] = mad(one_p * (1.0 - w), m.inv_tau_wm, -(p * w) * m.inv_tau_wp);
   }
+  // dv = alpha_v v + beta_v, dw = alpha_w w + beta_w (the same rates, sorted
+  // by powers of the gate).
+  template <class T>
+  __device__ __forceinline__ static void gates(const KConst& c, const T* y, T* al, T* be) {
+    const FentonKarmaC& m = c.m.fk;
+    const T u = y[0];
+    const T p = step_h(u - m.u_c, c);
+    const T q = step_h(u - m.u_v, c);
+    const T one_p = 1.0 - p;
+    const T r_vm = recip(mad(q, m.tau_v1m, (1.0 - q) * m.tau_v2m));
+    al[1] = -(one_p * r_vm) - p * m.inv_tau_vp;
+    be[1] = one_p * r_vm;
+    al[2] = -(one_p * m.inv_tau_wm) - p * m.inv_tau_wp;
+    be[2] = one_p * m.inv_tau_wm;
+  }
 };
 
 // Bueno-Orovio four-variable model, Eq. (5) with the currents and the
 // alpha/beta gate form; tau(u), v_inf, w_inf as in Bueno-Orovio et al. (2008).
 template <> struct Reaction<RD_MODEL_BOCF> {
+  // dv, dw as alpha g + beta (as the rates below form them); ds = (s_inf - s)/tau_s
+  // gives alpha_s = -1/tau_s, beta_s = s_inf/tau_s.
+  template <class T>
+  __device__ __forceinline__ static void gates(const KConst& c, const T* y, T* al, T* be) {
+    const BocfC& m = c.m.bo;
+    const T u = y[0];
+    const T h_v = step_h(u - m.th_v, c);
+    const T h_v_neg = step_h(m.th_v - u, c);
+    const T h_w = step_h(u - m.th_w, c);
+    const T h_w_neg = step_h(m.th_w - u, c);
+    const T h_vm = step_h(u - m.th_vm, c);
+    const T h_o = step_h(u - m.th_o, c);
+    const T r_vm = recip(mad(1.0 - h_vm, m.tau_v1m, h_vm * m.tau_v2m));
+    const T r_wm = recip(mad(m.dtau_wm, half_one_plus_tanh(m.k_wm * (u - m.u_wm)), T(m.tau_w1m)));
+    const T r_s = recip(mad(1.0 - h_w, m.tau_s1, h_w * m.tau_s2));
+    const T v_inf = step_h(m.th_vm - u, c);
+    const T w_inf = mad(1.0 - h_o, mad(-u, m.inv_tau_winf, 1.0), h_o * m.w_infstar);
+    al[1] = mad(-h_v, m.inv_tau_vp, -(h_v_neg * r_vm));
+    be[1] = (h_v_neg * v_inf) * r_vm;
+    al[2] = mad(-h_w, m.inv_tau_wp, -(h_w_neg * r_wm));
+    be[2] = (h_w_neg * w_inf) * r_wm;
+    al[3] = -r_s;
+    be[3] = half_one_plus_tanh(m.k_s * (u - m.u_s)) * r_s;
+  }
+
   template <class T>
   __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const BocfC& m = c.m.bo;
@@ -298,6 +368,48 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     f[3] = (half_one_plus_tanh(m.k_s * (u - m.u_s)) - s) * r_s;
   }
 };
+
+// One step of the gate schemes for a gate g with rate alpha g + beta frozen
+// over the step: GATE = 1 Rush-Larsen (exact for the frozen linear equation),
+// GATE = 2 implicit Euler.
+template <int GATE, class T>
+__device__ __forceinline__ T gate_step(T g, T al, T be, double dt) {
+  if constexpr (GATE == 1) {
+    const T x = al * dt;
+    return g * exp(x) + (be / al) * expm1(x);
+  } else {
+    return (g + dt * be) / (1.0 - dt * al);
+  }
+}
+
+// The step of a gate scheme on a packed row y (state, then tangent when TAN):
+// explicit Euler for the diffusive field with its full rate k (diffusion +
+// reaction), gate_step for the gates.  zn receives the new packed row.
+template <int MODEL, bool TAN, int GATE>
+__device__ __forceinline__ void gate_scheme_step(const KConst& c, const double* y, const double* k,
+                                                 double* zn) {
+  constexpr int NV = ModelTraits<MODEL>::NV;
+  static_assert(ModelTraits<MODEL>::GATED && ModelTraits<MODEL>::NDIFF == 1, "gated models only");
+  zn[0] = y[0] + c.dt * k[0];
+  if constexpr (!TAN) {
+    double al[NV], be[NV];
+    Reaction<MODEL>::template gates<double>(c, y, al, be);
+#pragma unroll
+    for (int g = 1; g < NV; ++g) zn[g] = gate_step<GATE>(y[g], al[g], be[g], c.dt);
+  } else {
+    zn[NV] = y[NV] + c.dt * k[NV];
+    Dual yd[NV], al[NV], be[NV];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) yd[f] = Dual(y[f], y[NV + f]);
+    Reaction<MODEL>::template gates<Dual>(c, yd, al, be);
+#pragma unroll
+    for (int g = 1; g < NV; ++g) {
+      const Dual r = gate_step<GATE>(yd[g], al[g], be[g], c.dt);
+      zn[g] = r.v;
+      zn[NV + g] = r.d;
+    }
+  }
+}
 
 // N(y) (TAN = false) or N(y) and J_N(y) dy (TAN = true) for a packed row
 // y[0..NV) = state, y[NV..2NV) = tangent; results packed the same way.

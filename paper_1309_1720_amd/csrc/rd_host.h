@@ -12,6 +12,7 @@ int hip_fail(hipError_t e, const char* what);
 int n_fields(int model);
 int n_params(int model);
 int n_stages(int scheme);
+bool gate_scheme(int scheme);  // Rush-Larsen or implicit Euler
 int validate(const rd_problem* p);
 int validate_fields(const rd_problem* p, double* const* f, const char* what);
 void derive_constants(const rd_problem* p, KConst& c);

@@ -99,18 +99,21 @@ template <int MODEL, int NS, int MODE> struct SweepPrefetch {
 
 // One wavefront's share of a sweep: strip wid / nby, band wid % nby of the
 // grid described by c, reading `in` and writing `out` (or the stage inputs
-// `ys`), advancing K steps (K > 1 only for the plain step).  Shared by the
-// single-grid and the batched kernels.
+// `ys`), advancing K steps (K > 1 only for the plain step).  GATE selects a
+// one-stage gate scheme (1 Rush-Larsen, 2 implicit Euler; NS = 1, gated
+// models) instead of explicit Euler.  Shared by the single-grid and the
+// batched kernels.
 //
 // K steps chain K copies of the one-step pipeline: copy k takes row r - k NS
 // of z_{n+k} (the row copy k - 1 finished in the same iteration; copy 0 the
 // row just loaded) and runs its stage s on row r - k NS - s, so the launch
 // needs KS = K NS halo columns and ramp rows.
-template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1>
+template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1, int GATE = 0>
 __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double* const* out,
                                                 double* const (*ys)[kMaxFields], const KConst& c,
                                                 int wid) {
   static_assert(K == 1 || MODE == kModeStep, "several steps per launch advance the state only");
+  static_assert(GATE == 0 || (NS == 1 && K == 1), "gate schemes have one stage");
   constexpr bool TAN = MODE == kModeTangent;
   constexpr bool STAGES = MODE == kModeStages;
   constexpr int NV = ModelTraits<MODEL>::NV;
@@ -294,13 +297,20 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         const bool last_core = out_col && (STEADY || (rho >= yA && rho < yB));
         if (NS == 1) {
           if (STAGES) continue;
+          double zn[NF];
+          if constexpr (GATE == 0) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) zn[f] = zr[k][1][f] + c.dt * kr[f];
+          } else {
+            gate_scheme_step<MODEL, TAN, GATE>(c, zr[k][1], kr, zn);
+          }
           if (!last) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) zout[f] = zr[k][1][f] + c.dt * kr[f];
+            for (int f = 0; f < NF; ++f) zout[f] = zn[f];
           } else if (last_core) {
             const size_t o = (size_t)rho * nx + gx;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) out[f][o] = zr[k][1][f] + c.dt * kr[f];
+            for (int f = 0; f < NF; ++f) out[f][o] = zn[f];
           }
           continue;
         }
@@ -362,33 +372,41 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 }
 
 // Strips that touch the grid's x-edges apply the mirror; interior strips skip it.
-template <int MODEL, int STENCIL, int NS, int MODE, int K = 1>
+template <int MODEL, int STENCIL, int NS, int MODE, int K = 1, int GATE = 0>
 __device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
                                            double* const (*ys)[kMaxFields], const KConst& c,
                                            int wid) {
   const int x0 = (wid / c.nby) * (kWave - 2 * K * NS) - K * NS;
   if (strip_touches_edge(x0, c))
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE>(in, out, ys, c, wid);
   else
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE>(in, out, ys, c, wid);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE, int K>
+template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE, K>::value)))
 void sweep_kernel(SweepArgs a) {
   const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
   const int wid = __builtin_amdgcn_readfirstlane(blk * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (wid >= a.c.nsx * a.c.nby) return;  // whole waves only: no barrier follows
-  sweep_wave<MODEL, STENCIL, NS, MODE, K>(a.in, a.out, a.ys, a.c, wid);
+  sweep_wave<MODEL, STENCIL, NS, MODE, K, GATE>(a.in, a.out, a.ys, a.c, wid);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE, int K>
+template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE = 0>
 hipError_t launch_sweep_k(const SweepArgs& a, hipStream_t stream) {
   const int waves = a.c.nsx * a.c.nby;
   const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE, K>), dim3(blocks), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE, K, GATE>), dim3(blocks), dim3(256), 0, stream, a);
   return hipGetLastError();
+}
+
+// One step of a gate scheme (gated models, state or state and tangent).
+template <int MODEL, int STENCIL, int MODE, int GATE>
+hipError_t launch_sweep_gate(const SweepArgs& a, hipStream_t stream) {
+  if constexpr (ModelTraits<MODEL>::GATED && MODE != kModeStages)
+    return launch_sweep_k<MODEL, STENCIL, 1, MODE, 1, GATE>(a, stream);
+  return hipErrorInvalidValue;
 }
 
 // One launch of a.c.ksteps steps (1 unless MultiStep allows more).
@@ -413,16 +431,22 @@ hipError_t launch_sweep_model(int stencil, int scheme, const SweepArgs& a, hipSt
       if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP5, 1, MODE>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP5, 2, MODE>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP5, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP5, MODE, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP5, MODE, 2>(a, s);
       break;
     case RD_LAP9:
       if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9, 1, MODE>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9, 2, MODE>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP9, MODE, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP9, MODE, 2>(a, s);
       break;
     case RD_LAP9_ANISO:
       if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9_ANISO, 1, MODE>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9_ANISO, 2, MODE>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9_ANISO, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP9_ANISO, MODE, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP9_ANISO, MODE, 2>(a, s);
       break;
   }
   return hipErrorInvalidValue;

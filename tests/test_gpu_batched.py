@@ -29,7 +29,8 @@ def batch_setup(model, stencil, scheme, steps, sizes=SIZES, seed=0):
 
 
 @pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rk4"), ("barkley", "lap5", "euler"),
-                                                  ("fhn", "lap9_aniso", "rk4"),
+                                                  ("fhn", "lap9_aniso", "rk4"), ("bocf", "lap9", "rush_larsen"),
+                                                  ("fk", "lap5", "implicit_euler"),
                                                   ("bocf", "lap9_aniso", "heun"), ("diffusion", "lap9", "rk4")])
 @pytest.mark.parametrize("steps", [1, 6])
 @pytest.mark.parametrize("tangent", [False, True])

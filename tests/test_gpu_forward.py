@@ -270,3 +270,24 @@ def test_bocf_convergence_orders_on_gpu(scheme, expected):
     """Table 1, Bueno-Orovio column: RK4 shows order 3 with the C1 step H_k."""
     orders = _gpu_orders("bocf_2048_aniso_rk4", "bocf", "lap9_aniso", scheme, 24, 8.0, 0.05, 5)
     assert abs(orders[-1] - expected) < 0.2, orders
+
+
+GATE_COMBOS = list(itertools.product(["fk", "bocf"], ["lap5", "lap9", "lap9_aniso"], ["rush_larsen", "implicit_euler"]))
+
+
+@pytest.mark.parametrize("model,stencil,scheme", GATE_COMBOS)
+def test_gate_schemes_match_oracle(model, stencil, scheme):
+    """Rush-Larsen and implicit Euler on the gates (Table 1 methods)."""
+    w = workload(model, stencil, scheme, 131, 77)
+    po, pr = problems(w, nsteps=37)
+    z0 = initial(model, w)
+    err = rel_linf(gpu_step(pr, z0), oracle.step(po, z0, 37))
+    print(f"{model} {stencil} {scheme}: rel-Linf {err:.3e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("scheme", ["rush_larsen", "implicit_euler"])
+def test_gate_scheme_orders_on_gpu(scheme):
+    """Table 1, Bueno-Orovio column: both gate schemes are first order."""
+    orders = _gpu_orders("bocf_2048_aniso_rk4", "bocf", "lap9_aniso", scheme, 24, 8.0, 0.05, 5)
+    assert abs(orders[-1] - 1) < 0.15, orders

@@ -53,6 +53,16 @@ def test_jvp_matches_oracle(model, stencil, scheme, variant):
     assert all(np.array_equal(a, b) for a, b in zip(z_gpu, z_fwd))
 
 
+@pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rush_larsen"), ("bocf", "lap9_aniso", "rush_larsen"),
+                                                  ("bocf", "lap5", "implicit_euler"), ("fk", "lap9_aniso", "implicit_euler")])
+def test_jvp_gate_schemes_match_oracle(model, stencil, scheme):
+    po, pr, z0, v = setup(model, stencil, scheme, 97, 61, 17)
+    z_ref, jv_ref = oracle.jvp(po, z0, v, 17)
+    z_gpu, jv_gpu = gpu_jvp(pr, z0, v)
+    assert rel_linf(z_gpu, z_ref) <= TOL
+    assert rel_linf(jv_gpu, jv_ref) <= TOL
+
+
 @pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rk4"), ("bocf", "lap5", "heun")])
 def test_jvp_heaviside_limit(model, stencil, scheme):
     """step_k = inf: the gates are piecewise constant, so their derivative

@@ -440,6 +440,40 @@ def test_bocf_orders_match_table1(scheme, key):
     assert abs(orders[-1] - expected) < 0.2, orders
 
 
+@pytest.mark.parametrize("scheme,key", [("rush_larsen", "rush_larsen"), ("implicit_euler", "implicit_euler")])
+def test_bocf_gate_schemes_orders_match_table1(scheme, key):
+    """Table 1: Rush-Larsen and implicit Euler (gates only) are first order."""
+    expected = table1()["observed"][key][2]
+    orders = richardson_orders("bocf", "lap9_aniso", scheme, 24, 8.0, 0.05, 5)
+    assert abs(orders[-1] - expected) < 0.15, orders
+
+
+@pytest.mark.parametrize("scheme", ["rush_larsen", "implicit_euler"])
+def test_gate_schemes_exact_on_resting_bocf(scheme):
+    """At rest (u = u_o = 0) the Bueno-Orovio voltage rate vanishes, so u stays
+    0 and each gate obeys dg/dt = alpha g + beta with constant coefficients.
+    Rush-Larsen reproduces the exact solution g_inf + (g0 - g_inf) e^{alpha t}
+    for any dt; implicit Euler its closed form g_inf + (g0 - g_inf) / (1 -
+    alpha dt)^n.  Also pins that each gate's rate is affine in the gate."""
+    dt, n = 0.7, 25
+    p = prob(model="bocf", scheme=scheme, stencil="lap5", nx=5, ny=4, dt=dt)
+    z0 = [np.full((4, 5), x) for x in (0.0, 0.3, 0.6, 0.8)]
+    coef = oracle.gate_coefficients(p, z0)
+    rates = oracle.reaction(p, z0)
+    out = oracle.step(p, z0, n)
+    assert np.all(out[0] == 0.0)
+    for g in (1, 2, 3):
+        a, b = coef[g]
+        assert np.max(np.abs(rates[g] - (a * z0[g] + b))) <= 1e-16
+        a, b = float(a[0, 0]), float(b[0, 0])
+        ginf, g0 = -b / a, float(z0[g][0, 0])
+        if scheme == "rush_larsen":
+            expect = ginf + (g0 - ginf) * math.exp(a * n * dt)
+        else:
+            expect = ginf + (g0 - ginf) / (1.0 - a * dt) ** n
+        assert np.max(np.abs(out[g] - expect)) <= 1e-14, (scheme, g)
+
+
 def test_sharp_heaviside_drops_rk4_to_first_order():
     """With the discontinuous step (k = inf) RK4 loses its order: the reason
     the paper smooths the step for derivative-based work."""
