@@ -185,7 +185,8 @@ int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents,
  *                lambda(nsteps), overwritten with
  *                lambda(0) = dPhi(z(0))^T lambda(nsteps).
  * States between checkpoints are recomputed into the workspace.
- * Supports RD_LAP5 and RD_LAP9 (RD_LAP9_ANISO returns RD_EUNSUPPORTED).
+ * All stencils: the anisotropic flux form, which is not symmetric, is
+ * transposed face by face (zero boundary flux and mirrored ghosts included).
  */
 int rd_vjp(const rd_problem* p, const double* checkpoints, double* const* cotangents,
            void* ws, size_t ws_bytes, void* hip_stream);

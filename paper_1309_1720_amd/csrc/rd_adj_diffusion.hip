@@ -1,4 +1,4 @@
-// Adjoint-step kernels of the diffusion model, 5- and 9-point stencils, all schemes.
+// Adjoint-step kernels of the diffusion model, all stencils and schemes.
 #include "rd_adjoint.h"
 
 namespace rd {

@@ -1,4 +1,4 @@
-// Adjoint-step kernels of the fk model, 5- and 9-point stencils, all schemes.
+// Adjoint-step kernels of the fk model, all stencils and schemes.
 #include "rd_adjoint.h"
 
 namespace rd {

@@ -9,7 +9,8 @@
 //   lam_n = lam + Ybar_S + ... + Ybar_1.
 // L is symmetric for the 5- and 9-point stencils with mirrored ghosts, so
 // L^T kbar_u is the same stencil applied to kbar_u (for every diffusive
-// field, each with its own diffusivity).  J_N(Y)^T comes from the
+// field, each with its own diffusivity).  The anisotropic flux form is not
+// symmetric; its transpose is applied in gather form (flux_transpose).  J_N(Y)^T comes from the
 // reaction's Jacobian columns, evaluated on dual numbers.
 //
 // The stage inputs Y_2 .. Y_S are produced beforehand by the stage-input mode
@@ -46,6 +47,74 @@ __device__ __forceinline__ void reaction_jt(const KConst& c, const double* y, co
     for (int m = 1; m < NV; ++m) acc = acc + kd[m].d * a[m];
     out[l] = acc;
   }
+}
+
+// Cross-flux coefficients D_xy/4 at the centres of the west and east
+// neighbour columns (the flux form's y-face terms reach them).
+struct ColumnNb {
+  double dxy_c4_w, dxy_c4_e;
+};
+__device__ __forceinline__ ColumnNb make_column_nb(int gx, const KConst& c) {
+  const double thw = c.theta0 + c.dtheta * (((double)(gx - 1) + 0.5) / c.n_total);
+  const double the = c.theta0 + c.dtheta * (((double)(gx + 1) + 0.5) / c.n_total);
+  ColumnNb nb;
+  nb.dxy_c4_w = 0.25 * ((c.dd * cos(thw)) * sin(thw));
+  nb.dxy_c4_e = 0.25 * ((c.dd * cos(the)) * sin(the));
+  return nb;
+}
+
+// (L^T a) at row J of this lane's column I for the anisotropic flux form
+// L = s D G (G: cell values -> face fluxes, D: face fluxes -> cell
+// divergence, zero flux through the boundary): with the face potentials
+// psi_x(i, j) = a(i, j) - a(i+1, j) and psi_y(i, j) = a(i, j) - a(i, j+1)
+// (= D^T a), every face flux formula scatters s psi times its coefficients
+// back to the cells it reads; gathered here per cell, including the cells a
+// mirrored (clamped) ghost index lands on.  up, cen, dn: a at rows J-1, J,
+// J+1 (values outside the grid are not used).  All lanes call it together.
+template <bool EDGE>
+__device__ __forceinline__ double flux_transpose(double up, double cen, double dn, const Column& col,
+                                                 const ColumnNb& nb, int J, const KConst& c, double s) {
+  const bool hasW = !(EDGE && col.west), hasE = !(EDGE && col.east);  // faces I-1/2, I+1/2 exist
+  const bool atW = EDGE && col.west, atE = EDGE && col.east;          // I == 0, I == nx-1
+  const bool hasU = J >= 1, hasD = J <= c.ny - 2;
+  // x-face potentials of the east face at rows J-1, J, J+1, and of the west face
+  const double pe_u = up - from_east(up), pe_c = cen - from_east(cen), pe_d = dn - from_east(dn);
+  const double pw_u = from_west(pe_u), pw_c = from_west(pe_c), pw_d = from_west(pe_d);
+  // y-face potentials of the faces above (J-1/2) and below (J+1/2), here and at I-1, I+1
+  const double py_u = up - cen, py_d = cen - dn;
+  const double pyw_u = from_west(py_u), pyw_d = from_west(py_d);
+  const double pye_u = from_east(py_u), pye_d = from_east(py_d);
+
+  double t = 0.0;
+  // x-faces: the u(i+1, j) - u(i, j) term
+  if (hasW) t += col.dxx_w * pw_c;
+  if (hasE) t -= col.dxx_e * pe_c;
+  // x-faces: cross terms (rows j+1 and j-1 of the face, clamped at the y-edges)
+  auto cross_x = [&](double q, double pu, double pc, double pd) {
+    double r = 0.0;
+    if (hasU) r += q * pu;
+    if (!hasD) r += q * pc;  // J == ny-1: the face's row j+1 is clamped to J
+    if (hasD) r -= q * pd;
+    if (!hasU) r -= q * pc;  // J == 0: the face's row j-1 is clamped to J
+    return r;
+  };
+  if (hasW) t += cross_x(col.dxy_w4, pw_u, pw_c, pw_d);
+  if (hasE) t += cross_x(col.dxy_e4, pe_u, pe_c, pe_d);
+  // y-faces: the u(i, j+1) - u(i, j) term
+  if (hasU) t += col.dyy_c * py_u;
+  if (hasD) t -= col.dyy_c * py_d;
+  // y-faces: cross terms, read at columns i+1 (clamped) and i-1 (clamped)
+  auto cross_y = [&](double r, double pu, double pd) {
+    double v = 0.0;
+    if (hasU) v += r * pu;
+    if (hasD) v += r * pd;
+    return v;
+  };
+  if (hasW) t += cross_y(nb.dxy_c4_w, pyw_u, pyw_d);  // face of column I-1 reads I as its east column
+  if (atE) t += cross_y(col.dxy_c4, py_u, py_d);      // I == nx-1: its own east column clamps to I
+  if (hasE) t -= cross_y(nb.dxy_c4_e, pye_u, pye_d);  // face of column I+1 reads I as its west column
+  if (atW) t -= cross_y(col.dxy_c4, py_u, py_d);      // I == 0: its own west column clamps to I
+  return t * s;
 }
 
 template <int NS> struct AdjCoef;
@@ -86,7 +155,9 @@ void adjoint_kernel(AdjArgs a) {
   const int gx = sx * TX - NS + lane;
   const int cx = min(max(gx, 0), c.nx - 1);
   const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;
-  const Column col = make_column(gx, c, false);
+  constexpr bool ANISO = STENCIL == RD_LAP9_ANISO;
+  const Column col = make_column(gx, c, ANISO);
+  const ColumnNb nb = ANISO ? make_column_nb(gx, c) : ColumnNb{0.0, 0.0};
   const bool edge = strip_touches_edge(sx * TX - NS, c);
 
   const int yA = by * c.ty;
@@ -189,8 +260,12 @@ void adjoint_kernel(AdjArgs a) {
       for (int d = 0; d < NDF; ++d) {
         if (rho == 0) up[d] = kb[d];
         if (rho == c.ny - 1) dn[d] = kb[d];
-        lapT[d] = edge ? diffusion<STENCIL, true>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d])
-                       : diffusion<STENCIL, false>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d]);
+        if constexpr (ANISO)
+          lapT[d] = edge ? flux_transpose<true>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d])
+                         : flux_transpose<false>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d]);
+        else
+          lapT[d] = edge ? diffusion<STENCIL, true>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d])
+                         : diffusion<STENCIL, false>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d]);
       }
 
       double y[NV];
@@ -250,6 +325,11 @@ hipError_t launch_adjoint_model(int stencil, int scheme, const AdjArgs& a, hipSt
       if (scheme == RD_SCHEME_EULER) return launch_adjoint<MODEL, RD_LAP9, 1>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_adjoint<MODEL, RD_LAP9, 2>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_adjoint<MODEL, RD_LAP9, 4>(a, s);
+      break;
+    case RD_LAP9_ANISO:
+      if (scheme == RD_SCHEME_EULER) return launch_adjoint<MODEL, RD_LAP9_ANISO, 1>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_adjoint<MODEL, RD_LAP9_ANISO, 2>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_adjoint<MODEL, RD_LAP9_ANISO, 4>(a, s);
       break;
   }
   return hipErrorInvalidValue;

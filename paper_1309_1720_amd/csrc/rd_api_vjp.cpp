@@ -43,8 +43,6 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
   if (rc) return rc;
   rc = validate_fields(p, cot, "cotangents");
   if (rc) return rc;
-  if (p->stencil == RD_LAP9_ANISO)
-    return fail(RD_EUNSUPPORTED, "rd_vjp supports the 5- and 9-point isotropic stencils");
   if (gate_scheme(p->scheme))
     return fail(RD_EUNSUPPORTED, "rd_vjp supports the Euler, Heun and RK4 schemes");
   if (p->checkpoint_every <= 0) return fail(RD_EINVAL, "rd_vjp needs checkpoint_every > 0");

@@ -17,7 +17,7 @@ TOL = 1e-11
 BASE = {"diffusion": "barkley_1024_rk4_adjoint", "barkley": "barkley_1024_rk4_adjoint",
         "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4", "fhn": "fhn_256_rk4"}
 CASES = [(m, st, sc) for m in ("barkley", "fk", "bocf", "diffusion", "fhn")
-         for st in ("lap5", "lap9") for sc in ("euler", "heun", "rk4")]
+         for st in ("lap5", "lap9", "lap9_aniso") for sc in ("euler", "heun", "rk4")]
 
 
 def setup(model, stencil, scheme, nx, ny, steps, every, seed=3):
@@ -81,7 +81,8 @@ def dot(a, b):
 
 
 @pytest.mark.parametrize("model,stencil,n,steps", [("barkley", "lap5", 256, 400), ("fk", "lap9", 192, 200),
-                                                   ("bocf", "lap9", 96, 60)])
+                                                   ("bocf", "lap9", 96, 60), ("bocf", "lap9_aniso", 96, 60),
+                                                   ("fhn", "lap9_aniso", 128, 200)])
 def test_dot_product_jvp_vjp(model, stencil, n, steps):
     po, pr, z0 = setup(model, stencil, "rk4", n, n, steps, 64, seed=5)
     nv = len(z0)
@@ -136,8 +137,18 @@ def test_autograd_flow_matches_oracle_gradient():
     assert rel_linf([u0.grad.cpu().numpy(), v0.grad.cpu().numpy()], ref) <= TOL
 
 
-def test_vjp_rejects_anisotropic_stencil():
-    po, pr, z0 = setup("bocf", "lap9_aniso", "rk4", 32, 32, 4, 2)
+@pytest.mark.parametrize("nx,ny", [(1, 7), (7, 1), (2, 3), (63, 9), (140, 33)])
+def test_vjp_anisotropic_degenerate_grids(nx, ny):
+    """The transposed flux form at single columns or rows (every face a
+    boundary face, ghosts clamped on both sides) and ragged strips."""
+    po, pr, z0 = setup("bocf", "lap9_aniso", "heun", nx, ny, 5, 2)
+    lam = ri.direction(4, nx, ny, 77)
+    ref = oracle.vjp(po, z0, lam, 5, checkpoint_every=2)
+    assert rel_linf(gpu_vjp(pr, z0, lam), ref) <= TOL
+
+
+def test_vjp_rejects_gate_schemes():
+    po, pr, z0 = setup("bocf", "lap5", "rush_larsen", 32, 32, 4, 2)
     ck = torch.zeros(2 * 4 * 32 * 32, dtype=torch.float64, device="cuda")
     with pytest.raises(rd.RDError, match="RD_EUNSUPPORTED"):
         rd.vjp(pr, ck, dev(z0))
