@@ -40,6 +40,18 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def measured_counters(cells: int, tile_rows: int):
+    """The committed counter record, if it was taken on the current kernel
+    sources with the band height in use; else None."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    with open(COUNTERS_FILE) as fh:
+        c = json.load(fh)
+    if c.get("kernel_sha") != kernel_hash() or c.get("cells") != cells or c.get("tile_rows") != tile_rows:
+        return None
+    return c
+
+
 def measured_traffic(cells: int, tile_rows: int):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
     taken on the current kernel sources with the band height in use; else
@@ -51,6 +63,23 @@ def measured_traffic(cells: int, tile_rows: int):
     if c.get("kernel_sha") != kernel_hash() or c.get("cells") != cells or c.get("tile_rows") != tile_rows:
         return None
     return c.get("hbm_bytes_per_launch")
+
+
+# Vector-instruction issue capacity: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (a wave64 VALU instruction, FP64 included, occupies a SIMD for 4 cycles).
+VALU_LANE_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def valu_issue(cells: int, tile_rows: int, launch_s: float):
+    """Measured lane-instructions per second of the fused step (counter
+    record x the live launch time) against the issue capacity."""
+    c = measured_counters(cells, tile_rows)
+    if not c or "valu_instructions_per_launch" not in c:
+        return None
+    achieved = c["valu_instructions_per_launch"] * 64 / launch_s
+    return {"achieved": achieved / 1e12, "peak": VALU_LANE_ISSUE_PEAK / 1e12, "unit": "T lane-instr/s",
+            "frac": achieved / VALU_LANE_ISSUE_PEAK,
+            "lane_instructions_per_cell_update": c["lane_instructions_per_cell_update"]}
 
 
 def cpu_baseline(w, params, seconds: float):
@@ -368,6 +397,7 @@ def main():
                          "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                          "frac": FK_RK4_FLOPS * rate / FP64_VECTOR_PEAK,
                          "flops_per_cell_update": FK_RK4_FLOPS},
+        "valu_issue": valu_issue(cells, tile_rows if variant == "sweep" else -1, launch_s),
         "kernel_variant": variant,
         "tile_rows": tile_rows,
         "wall_s": wall,

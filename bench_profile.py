@@ -106,6 +106,11 @@ def main(out: str, tile_rows: int) -> None:
 
     sq = _counters(os.path.join(out, "sq"))
     g = {c: _pick(sq, KERNEL, c) for c in SQ_COUNTERS}
+    rec["valu_instructions_per_launch"] = g["SQ_INSTS_VALU"]
+    rec["lane_instructions_per_cell_update"] = g["SQ_INSTS_VALU"] * 64 / cells
+    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
     waves = g["SQ_WAVES"]
     lines = ["# Fused RK4 step, Fenton-Karma 1024x1024 — hardware counters", "",
              "Commands (each a run of its own):", "",

@@ -61,11 +61,11 @@ def crop_windows(nx, ny, reach, size=48):
     return out
 
 
-def oracle_on_crops(w, z0, nsteps, reach):
+def oracle_on_crops(w, z0, nsteps, reach, size=48):
     """Oracle results on windows of a large grid (valid cells only)."""
     params = ri.params_array(w["model"])
     res = []
-    for x0, y0, cw, ch, valid in crop_windows(w["nx"], w["ny"], reach):
+    for x0, y0, cw, ch, valid in crop_windows(w["nx"], w["ny"], reach, size):
         pc = oracle.Problem.from_workload(dict(w, nx=cw, ny=ch), params=params, x0=x0,
                                           nx_total=w["nx"])
         out = oracle.step(pc, [a[y0:y0 + ch, x0:x0 + cw] for a in z0], nsteps)

@@ -291,3 +291,32 @@ def test_gate_scheme_orders_on_gpu(scheme):
     """Table 1, Bueno-Orovio column: both gate schemes are first order."""
     orders = _gpu_orders("bocf_2048_aniso_rk4", "bocf", "lap9_aniso", scheme, 24, 8.0, 0.05, 5)
     assert abs(orders[-1] - 1) < 0.15, orders
+
+
+@pytest.mark.slow
+def test_full_grid_fk_1024_thousand_steps_matches_oracle():
+    """The headline workload at its full size: 1024^2 Fenton-Karma, RK4,
+    1000 steps, the whole grid against the oracle (about 2 minutes of CPU)."""
+    w = ri.workload("fk_1024_rk4")
+    po, pr = problems(w, nsteps=1000)
+    z0 = ri.initial_condition(w)
+    got = gpu_step(pr, z0)
+    ref = oracle.step(po, z0, 1000)
+    err = rel_linf(got, ref)
+    print(f"fk 1024^2 1000 steps: rel-Linf {err:.3e}")
+    assert err <= TOL
+
+
+@pytest.mark.slow
+def test_full_grid_bocf_2048_windows_fifty_steps():
+    """The 2048^2 anisotropic Bueno-Orovio workload, 50 steps, checked on
+    windows at corners, edges and centre inside their light cones."""
+    w = ri.workload("bocf_2048_aniso_rk4")
+    _, pr = problems(w, nsteps=50)
+    z0 = ri.initial_condition(w)
+    got = gpu_step(pr, z0)
+    reach = 4 * 50 + 1
+    for (x0, y0, cw, ch, valid), out in oracle_on_crops(w, z0, 50, reach, size=2 * reach + 48):
+        g = [a[y0:y0 + ch, x0:x0 + cw][valid] for a in got]
+        err = rel_linf(g, [a[valid] for a in out])
+        assert err <= TOL, (x0, y0, err)
