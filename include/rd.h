@@ -96,8 +96,12 @@ enum rd_scheme {
  *                 zero flux through the domain boundary. */
 enum rd_stencil { RD_LAP5 = 5, RD_LAP9 = 9, RD_LAP9_ANISO = 10 };
 
-/* Boundary conditions: no-flux (Eq. 2) via mirrored ghost cells (Fig. 1). */
-enum rd_bc { RD_BC_NOFLUX = 0 };
+/* Boundary conditions: no-flux (Eq. 2) via mirrored ghost cells (Fig. 1),
+ * or periodic -- the alternative Sect. 3 describes, displacements that leave
+ * the domain mapping to the opposite edge (in the flux form every face is
+ * interior; the face between the last and the first column takes the tensor
+ * at x = nx dx). */
+enum rd_bc { RD_BC_NOFLUX = 0, RD_BC_PERIODIC = 1 };
 
 /* Operations, for rd_workspace_bytes(). */
 enum rd_op { RD_OP_STEP = 0, RD_OP_JVP = 1, RD_OP_VJP = 2, RD_OP_BATCHED = 3 };

@@ -15,6 +15,7 @@ import numpy as np
 MODELS = ("diffusion", "barkley", "fk", "bocf", "fhn")
 SCHEMES = ("euler", "heun", "rk4", "rush_larsen", "implicit_euler")
 STENCILS = ("lap5", "lap9", "lap9_aniso")
+BCS = ("noflux", "periodic")
 
 
 @dataclass(frozen=True)
@@ -34,6 +35,7 @@ class Problem:
     params: tuple = field(default_factory=tuple)
     x0: int = 0
     nx_total: int | None = None
+    bc: str = "noflux"
 
     def __post_init__(self):
         if self.model not in MODELS:
@@ -42,6 +44,8 @@ class Problem:
             raise ValueError(f"unknown scheme {self.scheme!r}")
         if self.stencil not in STENCILS:
             raise ValueError(f"unknown stencil {self.stencil!r}")
+        if self.bc not in BCS:
+            raise ValueError(f"unknown boundary condition {self.bc!r}")
         object.__setattr__(self, "params", tuple(float(p) for p in self.params))
 
     @property
@@ -55,7 +59,7 @@ class Problem:
     @classmethod
     def from_workload(cls, w: dict, params=None, **overrides) -> "Problem":
         keys = ("model", "scheme", "stencil", "nx", "ny", "dx", "dt", "D_par",
-                "D_perp", "theta0", "theta1", "step_k")
+                "D_perp", "theta0", "theta1", "step_k", "bc")
         kw = {k: w[k] for k in keys if k in w}
         kw["params"] = tuple(np.asarray(params, dtype=np.float64)) if params is not None else ()
         kw.update(overrides)

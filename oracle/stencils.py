@@ -19,6 +19,12 @@ gives exactly zero on a uniform field.
 5-point Laplacian: the canonical central-difference operator named in
 Sect. 3, (W + E + N + S - 4 C) / dx^2.
 
+Periodic boundaries (the alternative Sect. 3 describes: displacements that
+leave the domain map to the opposite edge): ghost cells take the values of
+the opposite edge, and in the flux form every face is interior, the face
+between the last and the first column included (its tensor is that of
+x = nx dx).
+
 Anisotropic tensor (extension of Eq. 1 to D = D_perp I + (D_par - D_perp) f f^T,
 f = (cos theta, sin theta), theta linear in x).  Conservative flux form:
 face fluxes F = D grad u on every interior face, zero flux on the domain
@@ -37,13 +43,14 @@ ALPHA_AXIAL = 2.0 / 3.0
 ALPHA_DIAG = 1.0 / 6.0
 
 
-def ghost_pad(u: np.ndarray) -> np.ndarray:
-    """Field with one ghost layer holding the adjacent boundary values (Fig. 1)."""
-    return np.pad(u, 1, mode="edge")
+def ghost_pad(u: np.ndarray, bc: str = "noflux") -> np.ndarray:
+    """Field with one ghost layer holding the adjacent boundary values (Fig. 1),
+    or the opposite edge's values for periodic boundaries."""
+    return np.pad(u, 1, mode="wrap" if bc == "periodic" else "edge")
 
 
-def _neighbours(u):
-    g = ghost_pad(u)
+def _neighbours(u, bc="noflux"):
+    g = ghost_pad(u, bc)
     return {
         "C": g[1:-1, 1:-1], "W": g[1:-1, :-2], "E": g[1:-1, 2:],
         "N": g[:-2, 1:-1], "S": g[2:, 1:-1],
@@ -51,15 +58,15 @@ def _neighbours(u):
     }
 
 
-def lap5(u: np.ndarray, c: float) -> np.ndarray:
+def lap5(u: np.ndarray, c: float, bc: str = "noflux") -> np.ndarray:
     """c * (W + E + N + S - 4 C), c = D / dx^2."""
-    n = _neighbours(u)
+    n = _neighbours(u, bc)
     return c * (((n["W"] + n["E"]) + (n["N"] + n["S"])) - 4.0 * n["C"])
 
 
-def lap9(u: np.ndarray, c: float) -> np.ndarray:
+def lap9(u: np.ndarray, c: float, bc: str = "noflux") -> np.ndarray:
     """Balanced isotropic 9-point stencil of Eq. (6), c = D / (dx dy)."""
-    n = _neighbours(u)
+    n = _neighbours(u, bc)
     axial = ((n["W"] + n["E"]) + (n["N"] + n["S"])) - 4.0 * n["C"]
     diag = ((n["NW"] + n["SW"]) + (n["NE"] + n["SE"])) - 4.0 * n["C"]
     return c * (ALPHA_AXIAL * axial + ALPHA_DIAG * diag)
@@ -92,6 +99,8 @@ def fibre_coefficients(prob: Problem):
 def lap_aniso(u: np.ndarray, prob: Problem, rel: float = 1.0) -> np.ndarray:
     """div(rel D grad u) in conservative flux form with zero boundary-face
     flux; the relative diffusivity rel scales the face-flux divergence."""
+    if prob.bc == "periodic":
+        return _lap_aniso_periodic(u, prob, rel)
     dxx_f, dxy_f, dxy_c, dyy_c = fibre_coefficients(prob)
     inv_dx2 = rel / (prob.dx * prob.dx)
     n = _neighbours(u)
@@ -110,15 +119,43 @@ def lap_aniso(u: np.ndarray, prob: Problem, rel: float = 1.0) -> np.ndarray:
     return ((fx_all[:, 1:] - fx_all[:, :-1]) + (fy_all[1:, :] - fy_all[:-1, :])) * inv_dx2
 
 
+def _periodic_tensor(prob: Problem):
+    """(Dxx, Dxy) at the nx faces i + 1/2 (the last one at x = nx dx) and
+    (Dxy, Dyy) at the centres, for the periodic flux form."""
+    n_tot = prob.n_total
+    gi = np.arange(prob.nx, dtype=np.float64) + prob.x0
+    dth = prob.theta1 - prob.theta0
+    th_c = prob.theta0 + dth * ((gi + 0.5) / n_tot)
+    th_f = prob.theta0 + dth * ((gi + 1.0) / n_tot)
+    dd = prob.D_par - prob.d_perp
+    cf, sf, cc, sc = np.cos(th_f), np.sin(th_f), np.cos(th_c), np.sin(th_c)
+    return prob.d_perp + dd * cf * cf, dd * cf * sf, dd * cc * sc, prob.d_perp + dd * sc * sc
+
+
+def _lap_aniso_periodic(u: np.ndarray, prob: Problem, rel: float) -> np.ndarray:
+    dxx_f, dxy_f, dxy_c, dyy_c = _periodic_tensor(prob)
+    inv_dx2 = rel / (prob.dx * prob.dx)
+    E = np.roll(u, -1, axis=1)            # u(i+1, j)
+    W = np.roll(u, 1, axis=1)             # u(i-1, j)
+    # x-face i+1/2 (between i and i+1, wrapping), all nx of them
+    fx = (dxx_f * (E - u)
+          + (0.25 * dxy_f) * ((np.roll(E, -1, axis=0) + np.roll(u, -1, axis=0))
+                              - (np.roll(E, 1, axis=0) + np.roll(u, 1, axis=0))))
+    # y-face j+1/2 (between j and j+1, wrapping), all ny of them
+    fy = ((0.25 * dxy_c) * ((np.roll(E, -1, axis=0) + E) - (np.roll(W, -1, axis=0) + W))
+          + dyy_c * (np.roll(u, -1, axis=0) - u))
+    return ((fx - np.roll(fx, 1, axis=1)) + (fy - np.roll(fy, 1, axis=0))) * inv_dx2
+
+
 def laplacian(prob: Problem, u: np.ndarray, rel: float = 1.0) -> np.ndarray:
     """Diffusion term of a field with diffusivity rel * D_par (rel = 1: the
-    voltage) for the problem's stencil."""
+    voltage) for the problem's stencil and boundary condition."""
     if prob.stencil == "lap9_aniso":
         return lap_aniso(u, prob, rel)
     c = (prob.D_par * rel) / (prob.dx * prob.dx)
     if prob.stencil == "lap5":
-        return lap5(u, c)
-    return lap9(u, c)
+        return lap5(u, c, prob.bc)
+    return lap9(u, c, prob.bc)
 
 
 # ---------------------------------------------------------------------------
@@ -132,6 +169,8 @@ def _clip(a, n):
 
 def laplacian_matrix(prob: Problem, rel: float = 1.0) -> sp.csr_matrix:
     """The operator `laplacian(prob, ., rel)` as a sparse matrix."""
+    if prob.bc == "periodic":
+        return _periodic_matrix(prob, rel)
     nx, ny = prob.nx, prob.ny
     ncell = nx * ny
     j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
@@ -220,3 +259,15 @@ def laplacian_matrix(prob: Problem, rel: float = 1.0) -> sp.csr_matrix:
     else:
         ly = sp.csr_matrix((ncell, ncell))
     return ((lx + ly) * inv_dx2).tocsr()
+
+
+def _periodic_matrix(prob: Problem, rel: float) -> sp.csr_matrix:
+    """Periodic operators, column by column: L e_k for every unit vector
+    (small grids only; the adjoint tests use it)."""
+    nx, ny = prob.nx, prob.ny
+    cols = []
+    for k in range(nx * ny):
+        e = np.zeros(nx * ny)
+        e[k] = 1.0
+        cols.append(sp.csr_matrix(laplacian(prob, e.reshape(ny, nx), rel).reshape(-1, 1)))
+    return sp.hstack(cols).tocsr()

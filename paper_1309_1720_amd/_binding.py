@@ -20,6 +20,7 @@ ABI_VERSION = 1
 
 MODELS = {"diffusion": 0, "barkley": 1, "fk": 2, "bocf": 3, "fhn": 4}
 SCHEMES = {"euler": 1, "heun": 2, "rk4": 4, "rush_larsen": 5, "implicit_euler": 6}
+BCS = {"noflux": 0, "periodic": 1}
 STENCILS = {"lap5": 5, "lap9": 9, "lap9_aniso": 10}
 OPS = {"step": 0, "jvp": 1, "vjp": 2, "batched": 3}
 N_FIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4, "fhn": 2}
@@ -117,6 +118,7 @@ class Problem:
     step_k: float = 28.4
     params: tuple = field(default_factory=tuple)
     checkpoint_every: int = 0
+    bc: str = "noflux"
 
     @property
     def nfields(self) -> int:
@@ -125,7 +127,7 @@ class Problem:
     @classmethod
     def from_workload(cls, w: dict, params, **overrides) -> "Problem":
         keys = ("model", "scheme", "stencil", "nx", "ny", "dx", "dt", "nsteps", "D_par",
-                "D_perp", "theta0", "theta1", "step_k", "checkpoint_every")
+                "D_perp", "theta0", "theta1", "step_k", "checkpoint_every", "bc")
         kw = {k: w[k] for k in keys if k in w}
         kw["params"] = tuple(float(x) for x in params)
         kw.update(overrides)
@@ -137,7 +139,7 @@ class Problem:
         buf = (C.c_double * max(n, 1))(*[float(x) for x in self.params])
         cp = _CProblem(
             abi_version=ABI_VERSION, model=MODELS[self.model], scheme=SCHEMES[self.scheme],
-            stencil=STENCILS[self.stencil], bc=0, nx=int(self.nx), ny=int(self.ny),
+            stencil=STENCILS[self.stencil], bc=BCS[self.bc], nx=int(self.nx), ny=int(self.ny),
             dx=float(self.dx), dt=float(self.dt), nsteps=int(self.nsteps),
             D_par=float(self.D_par),
             D_perp=float(self.D_par if self.D_perp is None else self.D_perp),

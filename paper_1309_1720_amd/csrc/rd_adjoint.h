@@ -55,8 +55,10 @@ struct ColumnNb {
   double dxy_c4_w, dxy_c4_e;
 };
 __device__ __forceinline__ ColumnNb make_column_nb(int gx, const KConst& c) {
-  const double thw = c.theta0 + c.dtheta * (((double)(gx - 1) + 0.5) / c.n_total);
-  const double the = c.theta0 + c.dtheta * (((double)(gx + 1) + 0.5) / c.n_total);
+  const int gw = c.periodic ? wrap_index(gx - 1, c.nx) : gx - 1;
+  const int ge = c.periodic ? wrap_index(gx + 1, c.nx) : gx + 1;
+  const double thw = c.theta0 + c.dtheta * (((double)gw + 0.5) / c.n_total);
+  const double the = c.theta0 + c.dtheta * (((double)ge + 0.5) / c.n_total);
   ColumnNb nb;
   nb.dxy_c4_w = 0.25 * ((c.dd * cos(thw)) * sin(thw));
   nb.dxy_c4_e = 0.25 * ((c.dd * cos(the)) * sin(the));
@@ -76,7 +78,7 @@ __device__ __forceinline__ double flux_transpose(double up, double cen, double d
                                                  const ColumnNb& nb, int J, const KConst& c, double s) {
   const bool hasW = !(EDGE && col.west), hasE = !(EDGE && col.east);  // faces I-1/2, I+1/2 exist
   const bool atW = EDGE && col.west, atE = EDGE && col.east;          // I == 0, I == nx-1
-  const bool hasU = J >= 1, hasD = J <= c.ny - 2;
+  const bool hasU = c.periodic || J >= 1, hasD = c.periodic || J <= c.ny - 2;
   // x-face potentials of the east face at rows J-1, J, J+1, and of the west face
   const double pe_u = up - from_east(up), pe_c = cen - from_east(cen), pe_d = dn - from_east(dn);
   const double pw_u = from_west(pe_u), pw_c = from_west(pe_c), pw_d = from_west(pe_d);
@@ -153,7 +155,7 @@ void adjoint_kernel(AdjArgs a) {
   const int sx = wid / c.nby;  // bands of one strip are consecutive
   const int by = wid % c.nby;
   const int gx = sx * TX - NS + lane;
-  const int cx = min(max(gx, 0), c.nx - 1);
+  const int cx = grid_index(gx, c.nx, c);
   const bool out_col = lane >= NS && lane < NS + TX && gx < c.nx;
   constexpr bool ANISO = STENCIL == RD_LAP9_ANISO;
   const Column col = make_column(gx, c, ANISO);
@@ -162,9 +164,9 @@ void adjoint_kernel(AdjArgs a) {
 
   const int yA = by * c.ty;
   const int yB = min(yA + c.ty, c.ny);
-  const int r_first = max(yA - NS, 0);
+  const int r_first = c.periodic ? yA - NS : max(yA - NS, 0);
   const int r_last = yB - 1 + NS;
-  const int load_end = min(yB + NS, c.ny);
+  const int load_end = c.periodic ? yB + NS : min(yB + NS, c.ny);
   const size_t nx = (size_t)c.nx;
 
   double lr[LR][NV];          // lr[a] = lambda_{n+1} at row r - a
@@ -194,7 +196,7 @@ void adjoint_kernel(AdjArgs a) {
   for (int f = 0; f < NV; ++f) pre[f] = 0.0;
   if (r_first < load_end) {
 #pragma unroll
-    for (int f = 0; f < NV; ++f) pre[f] = a.lam_in[f][(size_t)r_first * nx + cx];
+    for (int f = 0; f < NV; ++f) pre[f] = a.lam_in[f][(size_t)grid_index(r_first, c.ny, c) * nx + cx];
   }
 
   for (int r = r_first; r <= r_last; ++r) {
@@ -220,7 +222,7 @@ void adjoint_kernel(AdjArgs a) {
 #pragma unroll
       for (int f = 0; f < NV; ++f) lr[0][f] = pre[f];
       if (r + 1 < load_end) {
-        const size_t o = (size_t)(r + 1) * nx + cx;
+        const size_t o = (size_t)grid_index(r + 1, c.ny, c) * nx + cx;
 #pragma unroll
         for (int f = 0; f < NV; ++f) pre[f] = a.lam_in[f][o];
       }
@@ -230,8 +232,8 @@ void adjoint_kernel(AdjArgs a) {
     for (int j = NS; j >= 1; --j) {
       const int lag = NS - j + 1;
       const int rho = r - lag;
-      const int lo = max(yA - (j - 1), 0);
-      const int hi = min(yB + (j - 1), c.ny);
+      const int lo = c.periodic ? yA - (j - 1) : max(yA - (j - 1), 0);
+      const int hi = c.periodic ? yB + (j - 1) : min(yB + (j - 1), c.ny);
       if (rho < lo || rho >= hi) continue;  // wave-uniform
 
       // kbar_j at rows rho-1, rho, rho+1 (diffusive fields) and rho (all)
@@ -258,8 +260,8 @@ void adjoint_kernel(AdjArgs a) {
       double lapT[NDF];
 #pragma unroll
       for (int d = 0; d < NDF; ++d) {
-        if (rho == 0) up[d] = kb[d];
-        if (rho == c.ny - 1) dn[d] = kb[d];
+        if (!c.periodic && rho == 0) up[d] = kb[d];
+        if (!c.periodic && rho == c.ny - 1) dn[d] = kb[d];
         if constexpr (ANISO)
           lapT[d] = edge ? flux_transpose<true>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d])
                          : flux_transpose<false>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d]);
@@ -269,7 +271,7 @@ void adjoint_kernel(AdjArgs a) {
       }
 
       double y[NV];
-      const size_t o = (size_t)rho * nx + cx;
+      const size_t o = (size_t)grid_index(rho, c.ny, c) * nx + cx;
       if (j == 1) {
 #pragma unroll
         for (int f = 0; f < NV; ++f) y[f] = a.z[f][o];

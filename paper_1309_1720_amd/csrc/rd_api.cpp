@@ -76,7 +76,7 @@ int validate(const rd_problem* p) {
     return fail(RD_EUNSUPPORTED, "the Rush-Larsen and implicit-Euler schemes need a gated model (Fenton-Karma, Bueno-Orovio)");
   if (p->stencil != RD_LAP5 && p->stencil != RD_LAP9 && p->stencil != RD_LAP9_ANISO)
     return fail(RD_EINVAL, "unknown stencil %d", p->stencil);
-  if (p->bc != RD_BC_NOFLUX) return fail(RD_EINVAL, "unknown boundary condition %d", p->bc);
+  if (p->bc != RD_BC_NOFLUX && p->bc != RD_BC_PERIODIC) return fail(RD_EINVAL, "unknown boundary condition %d", p->bc);
   if (p->nx < 1 || p->ny < 1) return fail(RD_EINVAL, "grid %d x %d: both sides must be >= 1", p->nx, p->ny);
   if ((int64_t)p->nx * (int64_t)p->ny >= ((int64_t)1 << 31))
     return fail(RD_EINVAL, "grid %d x %d has 2^31 cells or more", p->nx, p->ny);
@@ -121,6 +121,7 @@ void derive_constants(const rd_problem* p, KConst& c) {
   c.nx = p->nx;
   c.ny = p->ny;
   c.ksteps = 1;
+  c.periodic = p->bc == RD_BC_PERIODIC ? 1 : 0;
   c.sharp = std::isinf(p->step_k) ? 1 : 0;
   c.k = p->step_k;
   c.k6 = c.sharp ? 0.0 : 6.0 * p->step_k;
@@ -235,7 +236,8 @@ hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const
       return pipe ? launch_pipe_stg_##name(stencil, scheme, a, s) : launch_sweep_stg_##name(stencil, scheme, a, s); \
   }                                                                                                \
   break;
-  const bool pipe = a.c.variant == kVariantPipe && !gate_scheme(scheme);  // gate schemes: sweep only
+  // the pipelined variant handles neither the gate schemes nor periodic rows
+  const bool pipe = a.c.variant == kVariantPipe && !gate_scheme(scheme) && !a.c.periodic;
   switch (model) {
     case RD_MODEL_DIFFUSION: RD_MODE_SWITCH(diffusion)
     case RD_MODEL_BARKLEY: RD_MODE_SWITCH(barkley)
@@ -347,7 +349,8 @@ void plan_geometry(const rd_problem* p, KConst& c, bool tangent, double* const* 
     return launch_sweep_mode(tangent ? kModeTangent : kModeStep, p->model, p->stencil, p->scheme, a, s);
   };
   const Plan pl = tuned_plan(tangent ? kTuneTangent : kTuneForward, p->model, p->stencil, p->scheme,
-                             p->nx, p->ny, ns, s, trial, !gate_scheme(p->scheme), 0, 0, kmax);
+                             p->nx, p->ny, ns, s, trial, !gate_scheme(p->scheme) && p->bc == RD_BC_NOFLUX,
+                             0, 0, kmax);
   c.variant = pl.variant;
   c.ksteps = pl.k;
   set_geometry(c, ns * pl.k, pl.ty);

@@ -48,6 +48,7 @@ struct KConst {
   int sharp;         // 1: Heaviside step instead of H_k
   int variant;       // fused-step kernel variant (StepVariant)
   int ksteps;        // steps per launch of the state-only sweep (1, 2, 4, 8)
+  int periodic;      // 1: periodic boundaries (RD_BC_PERIODIC), 0: no-flux
   double k;          // H_k sharpness (+inf for the Heaviside step)
   double k6;         // dH_k/dt scale 6 k (0 for the Heaviside step)
   double dt, h2, h6; // dt, dt/2, dt/6
@@ -462,9 +463,21 @@ struct Column {
 };
 
 // Whether the 64 columns of the strip starting at column x0 include the first
-// or the last column of the grid (wave-uniform).
+// or the last column of the grid (wave-uniform); periodic grids have no edge.
 __device__ __forceinline__ bool strip_touches_edge(int x0, const KConst& c) {
-  return x0 <= 0 || x0 + kWave - 1 >= c.nx - 1;
+  return !c.periodic && (x0 <= 0 || x0 + kWave - 1 >= c.nx - 1);
+}
+
+// x mod n in [0, n) for any int x (periodic indices).
+__device__ __forceinline__ int wrap_index(int x, int n) {
+  const int r = x % n;
+  return r < 0 ? r + n : r;
+}
+
+// The array index of column/row x: clamped into the grid for no-flux
+// boundaries (those values are mirrored or unused), wrapped for periodic ones.
+__device__ __forceinline__ int grid_index(int x, int n, const KConst& c) {
+  return c.periodic ? wrap_index(x, n) : min(max(x, 0), n - 1);
 }
 
 // Launch order -> work order.  Workgroups are handed to the eight XCDs
@@ -482,11 +495,14 @@ __device__ __forceinline__ int xcd_order(int b, int nblocks) {
 __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool aniso) {
   Column col;
   col.gx = gx;
-  col.west = gx <= 0;
-  col.east = gx >= c.nx - 1;
+  col.west = !c.periodic && gx <= 0;
+  col.east = !c.periodic && gx >= c.nx - 1;
   col.dxx_e = col.dxy_e4 = col.dxy_c4 = col.dyy_c = col.dxx_w = col.dxy_w4 = 0.0;
   if (aniso) {
-    const double g = (double)gx, gw = (double)(gx - 1);
+    // periodic: the tensor of the wrapped column (the face east of the last
+    // column lies at x = nx dx, as does the face west of the first)
+    const double g = c.periodic ? (double)wrap_index(gx, c.nx) : (double)gx;
+    const double gw = c.periodic ? (double)wrap_index(gx - 1, c.nx) : (double)(gx - 1);
     const double th_f = c.theta0 + c.dtheta * ((g + 1.0) / c.n_total);
     const double th_w = c.theta0 + c.dtheta * ((gw + 1.0) / c.n_total);
     const double th_c = c.theta0 + c.dtheta * ((g + 0.5) / c.n_total);
@@ -542,8 +558,8 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
     const double wDc = mw ? dn : wD, eDc = me ? dn : eD;
     double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (dn - cen);
     double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (cen - up);
-    if (YEDGE && rho == c.ny - 1) fys = 0.0;
-    if (YEDGE && rho == 0) fyn = 0.0;
+    if (YEDGE && !c.periodic && rho == c.ny - 1) fys = 0.0;
+    if (YEDGE && !c.periodic && rho == 0) fyn = 0.0;
     return ((fxe - fxw) + (fys - fyn)) * coef;
   }
 }
@@ -577,8 +593,8 @@ __device__ __forceinline__ double diffusion_rows(const double* up, const double*
     const double wCc = cen[iw], eCc = cen[ie], wUc = up[iw], eUc = up[ie], wDc = dn[iw], eDc = dn[ie];
     double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (d - C);
     double fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (C - u);
-    if (rho == c.ny - 1) fys = 0.0;
-    if (rho == 0) fyn = 0.0;
+    if (!c.periodic && rho == c.ny - 1) fys = 0.0;
+    if (!c.periodic && rho == 0) fyn = 0.0;
     return ((fxe - fxw) + (fys - fyn)) * coef;
   }
 }

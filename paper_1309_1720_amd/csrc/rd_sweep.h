@@ -131,15 +131,16 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   const int sx = wid / c.nby;  // bands of one strip are consecutive
   const int by = wid % c.nby;
   const int gx = sx * TX - KS + lane;
-  const int cx = min(max(gx, 0), c.nx - 1);
+  const int cx = grid_index(gx, c.nx, c);
   const bool out_col = lane >= KS && lane < KS + TX && gx < c.nx;
   const Column col = make_column(gx, c, STENCIL == RD_LAP9_ANISO);
 
   const int yA = by * c.ty;
   const int yB = min(yA + c.ty, c.ny);
-  const int r_first = max(yA - KS, 0);
+  // periodic grids run the ramps through the wrapped rows
+  const int r_first = c.periodic ? yA - KS : max(yA - KS, 0);
   const int r_last = yB - 1 + KS;
-  const int load_end = min(yB + KS, c.ny);
+  const int load_end = c.periodic ? yB + KS : min(yB + KS, c.ny);
   const size_t nx = (size_t)c.nx;
 
   // Per step copy k: register rings indexed by rows relative to its input row
@@ -176,7 +177,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   double pre[PF][NF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
-    const int row = min(r_first + p, load_end - 1);
+    const int row = grid_index(min(r_first + p, load_end - 1), c.ny, c);
 #pragma unroll
     for (int f = 0; f < NF; ++f) pre[p][f] = 0.0;
     if (row >= 0) {
@@ -229,7 +230,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 #pragma unroll
           for (int f = 0; f < NF; ++f) pre[p][f] = pre[p + 1][f];
       }
-      const size_t o = (size_t)min(r + PF, load_end - 1) * nx + cx;
+      const size_t o = (size_t)grid_index(min(r + PF, load_end - 1), c.ny, c) * nx + cx;
 #pragma unroll
       for (int f = 0; f < NF; ++f) pre[SLOT < 0 ? PF - 1 : q][f] = in[f][o];
     }
@@ -250,8 +251,8 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         if (STAGES && s == NS) continue;  // k_NS is not a stage input
         const int rho = r - k * NS - s;
         if (!STEADY) {
-          const int lo = max(yA - (K - k) * NS + s, 0);
-          const int hi = min(yB + (K - k) * NS - s, c.ny);
+          const int lo = c.periodic ? yA - (K - k) * NS + s : max(yA - (K - k) * NS + s, 0);
+          const int hi = c.periodic ? yB + (K - k) * NS - s : min(yB + (K - k) * NS - s, c.ny);
           if (rho < lo || rho >= hi) continue;  // wave-uniform
         }
 
@@ -278,8 +279,8 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         if (!STEADY) {
 #pragma unroll
           for (int d = 0; d < ND; ++d) {
-            if (rho == 0) up[d] = y[comp(d)];
-            if (rho == c.ny - 1) dn[d] = y[comp(d)];
+            if (!c.periodic && rho == 0) up[d] = y[comp(d)];
+            if (!c.periodic && rho == c.ny - 1) dn[d] = y[comp(d)];
           }
         }
 
@@ -355,7 +356,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   // between them goes PF rows at a time with fixed slots (its rows r + q sit
   // in slot q because the ring is in order when the run starts and ends).
   using Shift = std::integral_constant<int, -1>;
-  const int ss_lo = min(max(yA + KS, KS + 1), r_last + 1);
+  const int ss_lo = min(c.periodic ? yA + KS : max(yA + KS, KS + 1), r_last + 1);
   const int ss_hi = max(load_end, ss_lo);
   const int ss_end = ss_lo + (ss_hi - ss_lo) / PF * PF;
   int r = r_first;

@@ -35,7 +35,7 @@ def _flat(fields) -> torch.Tensor:
 
 def _physics(p: B.Problem):
     return (p.model, p.scheme, p.stencil, p.dx, p.dt, p.nsteps, p.D_par, p.D_perp, p.theta0, p.theta1,
-            p.step_k, tuple(p.params))
+            p.step_k, tuple(p.params), p.bc)
 
 
 def _batched(probs, members, fields, tans=None) -> None:

@@ -113,7 +113,7 @@ def workload(name: str, **overrides) -> dict:
     return w
 
 
-_BASE = dict(D_perp=None, theta0=0.0, theta1=0.0, step_k=STEP_K, checkpoint_every=0)
+_BASE = dict(D_perp=None, theta0=0.0, theta1=0.0, step_k=STEP_K, checkpoint_every=0, bc="noflux")
 
 _WORKLOADS = {
     # Barkley 128x128, 5-point Laplacian, forward Euler, 1000 steps.

@@ -71,7 +71,7 @@ def test_invalid_enums_and_params_rejected():
         assert rc == -1 and msg
     p = base_problem()
     cp, buf = p.to_c()
-    for fld, bad in (("model", 9), ("scheme", 3), ("stencil", 6), ("bc", 1), ("abi_version", 99)):
+    for fld, bad in (("model", 9), ("scheme", 3), ("stencil", 6), ("bc", 2), ("abi_version", 99)):
         q = B._CProblem.from_buffer_copy(cp)
         setattr(q, fld, bad)
         rc = B.lib().rd_step(C.byref(q), (C.c_void_p * 3)(1 << 16, 2 << 16, 3 << 16), None, 1 << 20, 1 << 30, None)

@@ -633,3 +633,60 @@ def test_inputs_are_seeded_and_in_range():
     assert len(s) == 4 and s[0].max() <= 1.0 + 1e-4
     f = ri.fhn_ic(40, 30, 6)
     assert np.array_equal(f[0], ri.fhn_ic(40, 30, 6)[0]) and f[0].max() <= 1.0 + 1e-3 and f[1].min() >= -0.5
+
+
+# ---------------------------------------------------------------------------
+# Periodic boundaries (the alternative of Sect. 3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("stencil", ["lap5", "lap9"])
+@pytest.mark.parametrize("mn", [(1, 0), (0, 2), (3, 1), (5, 4)])
+def test_periodic_fourier_modes_are_eigenvectors(stencil, mn):
+    nx, ny, dx, D = 12, 10, 0.4, 0.7
+    m, n = mn
+    a, b = 2 * math.pi * m / nx, 2 * math.pi * n / ny
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    phi = np.cos(a * i + 0.3) * np.cos(b * j - 0.2)
+    c = D / dx ** 2
+    if stencil == "lap5":
+        lam = c * ((2 * math.cos(a) - 2) + (2 * math.cos(b) - 2))
+    else:
+        lam = c * ((2 / 3) * (2 * math.cos(a) + 2 * math.cos(b) - 4) + (1 / 6) * (4 * math.cos(a) * math.cos(b) - 4))
+    lap = oracle.laplacian(prob(stencil=stencil, nx=nx, ny=ny, dx=dx, D_par=D, bc="periodic"), phi)
+    assert np.max(np.abs(lap - lam * phi)) <= 1e-13 * max(abs(lam), c)
+
+
+@pytest.mark.parametrize("ab", [(1, 0), (0, 1), (2, 3), (5, 1)])
+def test_periodic_flux_form_plane_wave_eigenvalue(ab):
+    """Constant fibre angle: the periodic flux form maps the plane wave
+    e^{i(a i + b j)} to lambda times itself, lambda from the face fluxes in
+    closed form."""
+    nx, ny, dx = 12, 8, 0.3
+    th, dpar, dperp = 0.6, 1.3, 0.4
+    a, b = 2 * math.pi * ab[0] / nx, 2 * math.pi * ab[1] / ny
+    p = prob(stencil="lap9_aniso", nx=nx, ny=ny, dx=dx, D_par=dpar, D_perp=dperp, theta0=th, theta1=th,
+             bc="periodic")
+    dd = dpar - dperp
+    dxx, dxy, dyy = dperp + dd * math.cos(th) ** 2, dd * math.cos(th) * math.sin(th), dperp + dd * math.sin(th) ** 2
+    q = dxy / 4
+    ea, eb = np.exp(1j * a), np.exp(1j * b)
+    lam = ((dxx * (ea - 1) + q * (ea + 1) * (eb - 1 / eb)) * (1 - 1 / ea)
+           + (q * (ea - 1 / ea) * (eb + 1) + dyy * (eb - 1)) * (1 - 1 / eb)) / dx ** 2
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    u = np.exp(1j * (a * i + b * j))
+    out = oracle.laplacian(p, u)
+    assert np.max(np.abs(out - lam * u)) <= 1e-12 * max(abs(lam), 1.0 / dx ** 2)
+
+
+@pytest.mark.parametrize("stencil", ["lap5", "lap9", "lap9_aniso"])
+def test_periodic_conserves_sum_and_commutes_with_shifts(stencil):
+    nx, ny = 11, 9
+    p = prob(stencil=stencil, scheme="rk4", nx=nx, ny=ny, dx=0.5, dt=0.01, D_par=1.0, D_perp=0.3,
+             theta0=0.4, theta1=0.4, bc="periodic")
+    u = np.random.default_rng(5).random((ny, nx))
+    out = oracle.step(p, [u], 50)[0]
+    assert abs(out.sum() - u.sum()) <= 1e-13 * u.sum()
+    shifted = oracle.step(p, [np.roll(np.roll(u, 3, axis=1), -2, axis=0)], 50)[0]
+    assert np.allclose(shifted, np.roll(np.roll(out, 3, axis=1), -2, axis=0), rtol=0, atol=1e-15)
