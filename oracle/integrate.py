@@ -132,12 +132,12 @@ def _check_state(prob: Problem, z):
     if len(z) != nv:
         raise ValueError(f"{prob.model} has {nv} fields, got {len(z)}")
     for a in z:
-        if np.shape(a) != (prob.ny, prob.nx):
-            raise ValueError(f"field shape {np.shape(a)} != {(prob.ny, prob.nx)}")
+        if np.shape(a) != prob.shape:
+            raise ValueError(f"field shape {np.shape(a)} != {prob.shape}")
 
 
 def step(prob: Problem, z, nsteps: int = 1):
-    """Advance state ``z`` (list of (ny, nx) arrays) by ``nsteps`` steps."""
+    """Advance state ``z`` (list of arrays of shape ``prob.shape``) by ``nsteps`` steps."""
     _check_state(prob, z)
     z = [np.array(a, copy=True) for a in z]
     for _ in range(int(nsteps)):

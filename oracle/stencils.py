@@ -25,6 +25,23 @@ the opposite edge, and in the flux form every face is interior, the face
 between the last and the first column included (its tensor is that of
 x = nx dx).
 
+3-D stencils (the conclusion looks ahead to three-dimensional tissue; the
+paper prints no 3-D operator).  Arrays are indexed [k, j, i] (k is z).  The
+27 cells of the 3 x 3 x 3 block around a cell fall into faces (6, one
+coordinate differs), edges (12, two differ) and corners (8, three differ);
+L u = c (w_f (sum faces - 6 C) + w_e (sum edges - 12 C) + w_c (sum corners
+- 8 C)), each group differenced against its own multiple of the centre as in
+the 9-point operator.  Consistency requires w_f + 4 w_e + 4 w_c = 1 and an
+isotropic leading error ((dx^2/12) lap^2 u, as for Eq. 6) requires
+w_f = 2 w_e + 8 w_c: a one-parameter family in w_c, every member of which
+reduces on a single plane with mirrored neighbours to the 2-D stencil of
+Eq. 6 (axial 2/3, diagonal 1/6).
+  lap7  : w = (1, 0, 0)            the canonical central difference
+  lap19 : w = (1/3, 1/6, 0)        the isotropic member without corners
+  lap27 : w = (7/15, 1/10, 1/30)   the compact (Mehrstellen) member
+Ghost layers follow the 2-D rules in every direction (mirror for no-flux,
+opposite face for periodic), corner and edge ghosts included.
+
 Anisotropic tensor (extension of Eq. 1 to D = D_perp I + (D_par - D_perp) f f^T,
 f = (cos theta, sin theta), theta linear in x).  Conservative flux form:
 face fluxes F = D grad u on every interior face, zero flux on the domain
@@ -41,6 +58,8 @@ from .problem import Problem
 
 ALPHA_AXIAL = 2.0 / 3.0
 ALPHA_DIAG = 1.0 / 6.0
+WEIGHTS_3D = {"lap7": (1.0, 0.0, 0.0), "lap19": (1.0 / 3.0, 1.0 / 6.0, 0.0),
+              "lap27": (7.0 / 15.0, 1.0 / 10.0, 1.0 / 30.0)}
 
 
 def ghost_pad(u: np.ndarray, bc: str = "noflux") -> np.ndarray:
@@ -147,9 +166,33 @@ def _lap_aniso_periodic(u: np.ndarray, prob: Problem, rel: float) -> np.ndarray:
     return ((fx - np.roll(fx, 1, axis=1)) + (fy - np.roll(fy, 1, axis=0))) * inv_dx2
 
 
+def lap3d(u: np.ndarray, c: float, weights, bc: str = "noflux") -> np.ndarray:
+    """3-D isotropic operator on an (nz, ny, nx) field:
+    c (w_f (faces - 6 C) + w_e (edges - 12 C) + w_c (corners - 8 C)), groups
+    with zero weight left out."""
+    g = ghost_pad(u, bc)
+    nz, ny, nx = u.shape
+    centre = g[1:-1, 1:-1, 1:-1]
+    sums = {1: 0.0, 2: 0.0, 3: 0.0}
+    for dk in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                m = abs(dk) + abs(dj) + abs(di)
+                if m:
+                    sums[m] = sums[m] + g[1 + dk:1 + dk + nz, 1 + dj:1 + dj + ny, 1 + di:1 + di + nx]
+    count = {1: 6.0, 2: 12.0, 3: 8.0}
+    out = 0.0
+    for m, w in zip((1, 2, 3), weights):
+        if w != 0.0:
+            out = out + w * (sums[m] - count[m] * centre)
+    return c * out
+
+
 def laplacian(prob: Problem, u: np.ndarray, rel: float = 1.0) -> np.ndarray:
     """Diffusion term of a field with diffusivity rel * D_par (rel = 1: the
     voltage) for the problem's stencil and boundary condition."""
+    if prob.is_3d:
+        return lap3d(u, (prob.D_par * rel) / (prob.dx * prob.dx), WEIGHTS_3D[prob.stencil], prob.bc)
     if prob.stencil == "lap9_aniso":
         return lap_aniso(u, prob, rel)
     c = (prob.D_par * rel) / (prob.dx * prob.dx)
@@ -169,8 +212,8 @@ def _clip(a, n):
 
 def laplacian_matrix(prob: Problem, rel: float = 1.0) -> sp.csr_matrix:
     """The operator `laplacian(prob, ., rel)` as a sparse matrix."""
-    if prob.bc == "periodic":
-        return _periodic_matrix(prob, rel)
+    if prob.bc == "periodic" or prob.is_3d:
+        return _matrix_by_columns(prob, rel)
     nx, ny = prob.nx, prob.ny
     ncell = nx * ny
     j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
@@ -261,13 +304,13 @@ def laplacian_matrix(prob: Problem, rel: float = 1.0) -> sp.csr_matrix:
     return ((lx + ly) * inv_dx2).tocsr()
 
 
-def _periodic_matrix(prob: Problem, rel: float) -> sp.csr_matrix:
-    """Periodic operators, column by column: L e_k for every unit vector
-    (small grids only; the adjoint tests use it)."""
-    nx, ny = prob.nx, prob.ny
+def _matrix_by_columns(prob: Problem, rel: float) -> sp.csr_matrix:
+    """Periodic and 3-D operators, column by column: L e_k for every unit
+    vector (small grids only; the adjoint tests use it)."""
+    n = int(np.prod(prob.shape))
     cols = []
-    for k in range(nx * ny):
-        e = np.zeros(nx * ny)
+    for k in range(n):
+        e = np.zeros(n)
         e[k] = 1.0
-        cols.append(sp.csr_matrix(laplacian(prob, e.reshape(ny, nx), rel).reshape(-1, 1)))
+        cols.append(sp.csr_matrix(laplacian(prob, e.reshape(prob.shape), rel).reshape(-1, 1)))
     return sp.hstack(cols).tocsr()

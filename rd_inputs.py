@@ -278,20 +278,23 @@ def initial_condition(w: dict) -> list[np.ndarray]:
     raise ValueError(f"unknown initial condition {kind!r}")
 
 
-def random_fields(model: str, nx: int, ny: int, seed: int) -> list[np.ndarray]:
-    """Random state inside the physiological range of ``model`` (tests)."""
+def random_fields(model: str, nx: int, ny: int, seed: int, nz: int | None = None) -> list[np.ndarray]:
+    """Random state inside the physiological range of ``model`` (tests);
+    arrays of shape (ny, nx), or (nz, ny, nx) when nz is given."""
     rng = np.random.default_rng(seed)
     nv = N_FIELDS[model]
+    shape = (ny, nx) if nz is None else (nz, ny, nx)
     if model == "fhn":  # u in (-1.2, 1.2), v in (-0.6, 0.6)
-        return [(rng.random((ny, nx)) - 0.5) * 2.4, (rng.random((ny, nx)) - 0.5) * 1.2]
+        return [(rng.random(shape) - 0.5) * 2.4, (rng.random(shape) - 0.5) * 1.2]
     hi = {"diffusion": 1.0, "barkley": 1.0, "fk": 1.0, "bocf": 1.55}[model]
-    u = rng.random((ny, nx)) * hi
-    return [u] + [rng.random((ny, nx)) for _ in range(nv - 1)]
+    u = rng.random(shape) * hi
+    return [u] + [rng.random(shape) for _ in range(nv - 1)]
 
 
-def direction(nfields: int, nx: int, ny: int, seed: int) -> list[np.ndarray]:
+def direction(nfields: int, nx: int, ny: int, seed: int, nz: int | None = None) -> list[np.ndarray]:
     """Gaussian direction over all fields, scaled to unit Euclidean norm."""
     rng = np.random.default_rng(seed)
-    d = [rng.standard_normal((ny, nx)) for _ in range(nfields)]
+    shape = (ny, nx) if nz is None else (nz, ny, nx)
+    d = [rng.standard_normal(shape) for _ in range(nfields)]
     nrm = math.sqrt(sum(float(np.sum(a * a)) for a in d))
     return [a / nrm for a in d]
