@@ -1,6 +1,6 @@
 /*
  * rd.h -- C ABI of librd.so, an MI355X (gfx950) library that advances 2-D
- * cardiac reaction-diffusion systems
+ * (and 3-D) cardiac reaction-diffusion systems
  *
  *     dz/dt = div(D grad z) + N[z],   z = (u, h1, h2, ...),
  *
@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define RD_ABI_VERSION 1
+#define RD_ABI_VERSION 2
 
 /* Models (Sect. 2; the Barkley and Fenton-Karma models are additions). */
 enum rd_model {
@@ -93,8 +93,22 @@ enum rd_scheme {
  *   RD_LAP9_ANISO div(D grad u) in conservative flux form for the tensor
  *                 D = D_perp I + (D_par - D_perp) f f^T, f = (cos t, sin t),
  *                 t linear in x from theta0 (x = 0) to theta1 (x = nx dx);
- *                 zero flux through the domain boundary. */
-enum rd_stencil { RD_LAP5 = 5, RD_LAP9 = 9, RD_LAP9_ANISO = 10 };
+ *                 zero flux through the domain boundary.
+ * 3-D operators on an nx x ny x nz grid (spacing dx in every direction; the
+ * paper's conclusion anticipates 3-D tissue but prints no 3-D stencil).  The
+ * 26 neighbours split into faces (6), edges (12) and corners (8); the operator
+ * is D/dx^2 (w_f (faces - 6C) + w_e (edges - 12C) + w_c (corners - 8C)) with
+ *   RD_LAP7   w = (1, 0, 0)           central differences
+ *   RD_LAP19  w = (1/3, 1/6, 0)       isotropic leading error, no corners
+ *   RD_LAP27  w = (7/15, 1/10, 1/30)  isotropic leading error, compact
+ * Both isotropic members reduce to Eq. (6) on a single plane with mirrored
+ * z-neighbours, as RD_LAP7 reduces to RD_LAP5.  Boundaries as in 2-D, in all
+ * three directions.  rd_step and rd_jvp take them (every model and scheme);
+ * rd_vjp and rd_step_batched return RD_EUNSUPPORTED. */
+enum rd_stencil {
+  RD_LAP5 = 5, RD_LAP9 = 9, RD_LAP9_ANISO = 10,
+  RD_LAP7 = 7, RD_LAP19 = 19, RD_LAP27 = 27
+};
 
 /* Boundary conditions: no-flux (Eq. 2) via mirrored ghost cells (Fig. 1),
  * or periodic -- the alternative Sect. 3 describes, displacements that leave
@@ -136,6 +150,9 @@ typedef struct rd_problem {
   int32_t checkpoint_every; /* rd_step: store the state every this many steps
                              into `checkpoints` (0 = none); rd_vjp: the
                              spacing of the checkpoints it is given            */
+  int32_t nz;             /* planes: 1 for the 2-D stencils; >= 1 for the 3-D
+                             ones, with nx * ny * nz < 2^40.  A 3-D field is
+                             stored [nz][ny][nx], x fastest                   */
 } rd_problem;
 
 /* ABI version the library was built with (RD_ABI_VERSION). */
@@ -150,7 +167,7 @@ int rd_n_params(int32_t model);
 /* Number of checkpoint states rd_step writes for this problem:
  * ceil(nsteps / checkpoint_every), 0 when checkpoint_every == 0.
  * Checkpoint m is the state after m * checkpoint_every steps, stored as
- * [m][field][ny][nx]. */
+ * [m][field][ny][nx] ([m][field][nz][ny][nx] in 3-D). */
 int rd_checkpoint_count(const rd_problem* p, int64_t* out);
 
 /* Bytes of device workspace `op` needs for problem `p` (for RD_OP_BATCHED,

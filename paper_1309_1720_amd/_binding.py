@@ -16,12 +16,13 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librd.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 MODELS = {"diffusion": 0, "barkley": 1, "fk": 2, "bocf": 3, "fhn": 4}
 SCHEMES = {"euler": 1, "heun": 2, "rk4": 4, "rush_larsen": 5, "implicit_euler": 6}
 BCS = {"noflux": 0, "periodic": 1}
-STENCILS = {"lap5": 5, "lap9": 9, "lap9_aniso": 10}
+STENCILS = {"lap5": 5, "lap9": 9, "lap9_aniso": 10, "lap7": 7, "lap19": 19, "lap27": 27}
+STENCILS_3D = ("lap7", "lap19", "lap27")
 OPS = {"step": 0, "jvp": 1, "vjp": 2, "batched": 3}
 N_FIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4, "fhn": 2}
 
@@ -42,7 +43,7 @@ class _CProblem(C.Structure):
         ("D_par", C.c_double), ("D_perp", C.c_double), ("theta0", C.c_double),
         ("theta1", C.c_double), ("step_k", C.c_double),
         ("params", C.POINTER(C.c_double)), ("nparams", C.c_int32),
-        ("checkpoint_every", C.c_int32),
+        ("checkpoint_every", C.c_int32), ("nz", C.c_int32),
     ]
 
 
@@ -119,15 +120,25 @@ class Problem:
     params: tuple = field(default_factory=tuple)
     checkpoint_every: int = 0
     bc: str = "noflux"
+    nz: int = 1
 
     @property
     def nfields(self) -> int:
         return N_FIELDS[self.model]
 
+    @property
+    def shape(self) -> tuple:
+        """Shape of one field tensor: (nz, ny, nx) for the 3-D stencils, else (ny, nx)."""
+        return (self.nz, self.ny, self.nx) if self.stencil in STENCILS_3D else (self.ny, self.nx)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
     @classmethod
     def from_workload(cls, w: dict, params, **overrides) -> "Problem":
         keys = ("model", "scheme", "stencil", "nx", "ny", "dx", "dt", "nsteps", "D_par",
-                "D_perp", "theta0", "theta1", "step_k", "checkpoint_every", "bc")
+                "D_perp", "theta0", "theta1", "step_k", "checkpoint_every", "bc", "nz")
         kw = {k: w[k] for k in keys if k in w}
         kw["params"] = tuple(float(x) for x in params)
         kw.update(overrides)
@@ -145,7 +156,7 @@ class Problem:
             D_perp=float(self.D_par if self.D_perp is None else self.D_perp),
             theta0=float(self.theta0), theta1=float(self.theta1), step_k=float(self.step_k),
             params=C.cast(buf, C.POINTER(C.c_double)), nparams=n,
-            checkpoint_every=int(self.checkpoint_every))
+            checkpoint_every=int(self.checkpoint_every), nz=int(self.nz))
         return cp, buf
 
 
@@ -155,9 +166,9 @@ def _ptrs(tensors, prob: Problem, what: str):
     for t in tensors:
         if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise ValueError(f"{what}: expected HIP device tensors")
-        if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (prob.ny, prob.nx):
+        if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != prob.shape:
             raise ValueError(f"{what}: expected contiguous float64 tensors of shape "
-                             f"{(prob.ny, prob.nx)}, got {t.dtype} {tuple(t.shape)}")
+                             f"{prob.shape}, got {t.dtype} {tuple(t.shape)}")
     arr = (C.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
     return arr
 
@@ -296,7 +307,7 @@ def set_autotune(enable: bool) -> None:
 
 
 def step(prob: Problem, fields, checkpoints: torch.Tensor | None = None):
-    """Advance ``fields`` (list of (ny, nx) float64 device tensors) in place by
+    """Advance ``fields`` (list of float64 device tensors of shape ``prob.shape``) in place by
     ``prob.nsteps`` steps; optionally store checkpoints (see rd_step)."""
     L = lib()
     f = _ptrs(fields, prob, "fields")
@@ -304,7 +315,7 @@ def step(prob: Problem, fields, checkpoints: torch.Tensor | None = None):
     cp, _buf = prob.to_c()
     ckpt = 0
     if checkpoints is not None:
-        need = checkpoint_count(prob) * prob.nfields * prob.nx * prob.ny
+        need = checkpoint_count(prob) * prob.nfields * prob.cells
         if (not checkpoints.is_cuda or checkpoints.dtype != torch.float64
                 or not checkpoints.is_contiguous() or checkpoints.numel() < need):
             raise ValueError(f"checkpoints: need a contiguous float64 device tensor of >= {need} elements")
@@ -334,7 +345,7 @@ def vjp(prob: Problem, checkpoints: torch.Tensor, cotangents):
     cp, _buf = prob.to_c()
     if not checkpoints.is_cuda or checkpoints.dtype != torch.float64 or not checkpoints.is_contiguous():
         raise ValueError("checkpoints: expected a contiguous float64 device tensor")
-    need = checkpoint_count(prob) * prob.nfields * prob.nx * prob.ny
+    need = checkpoint_count(prob) * prob.nfields * prob.cells
     if checkpoints.numel() < need:
         raise ValueError(f"checkpoints: need >= {need} elements, got {checkpoints.numel()}")
     ws, wsp = _workspace(workspace_bytes(prob, "vjp"), dev)

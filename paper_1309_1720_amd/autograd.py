@@ -19,7 +19,7 @@ class RDFlow(torch.autograd.Function):
             p.checkpoint_every = 64
         z = [f.detach().contiguous().clone() for f in fields]
         nck = B.checkpoint_count(p)
-        ck = torch.empty(max(nck, 1) * p.nfields * p.ny * p.nx, dtype=torch.float64,
+        ck = torch.empty(max(nck, 1) * p.nfields * p.cells, dtype=torch.float64,
                          device=z[0].device)
         B.step(p, z, ck)
         ctx.save_for_backward(ck)
@@ -30,7 +30,7 @@ class RDFlow(torch.autograd.Function):
     def backward(ctx, *grads):
         (ck,) = ctx.saved_tensors
         p = ctx.prob
-        lam = [torch.zeros((p.ny, p.nx), dtype=torch.float64, device=ck.device) if g is None
+        lam = [torch.zeros(p.shape, dtype=torch.float64, device=ck.device) if g is None
                else g.detach().contiguous().clone() for g in grads]
         B.vjp(p, ck, lam)
         return (None, *lam)

@@ -74,12 +74,19 @@ int validate(const rd_problem* p) {
   if (n_stages(p->scheme) < 0) return fail(RD_EINVAL, "unknown scheme %d", p->scheme);
   if (gate_scheme(p->scheme) && p->model != RD_MODEL_FENTON_KARMA && p->model != RD_MODEL_BOCF)
     return fail(RD_EUNSUPPORTED, "the Rush-Larsen and implicit-Euler schemes need a gated model (Fenton-Karma, Bueno-Orovio)");
-  if (p->stencil != RD_LAP5 && p->stencil != RD_LAP9 && p->stencil != RD_LAP9_ANISO)
+  if (p->stencil != RD_LAP5 && p->stencil != RD_LAP9 && p->stencil != RD_LAP9_ANISO && !is_3d(p->stencil))
     return fail(RD_EINVAL, "unknown stencil %d", p->stencil);
   if (p->bc != RD_BC_NOFLUX && p->bc != RD_BC_PERIODIC) return fail(RD_EINVAL, "unknown boundary condition %d", p->bc);
   if (p->nx < 1 || p->ny < 1) return fail(RD_EINVAL, "grid %d x %d: both sides must be >= 1", p->nx, p->ny);
   if ((int64_t)p->nx * (int64_t)p->ny >= ((int64_t)1 << 31))
     return fail(RD_EINVAL, "grid %d x %d has 2^31 cells or more", p->nx, p->ny);
+  if (is_3d(p->stencil)) {
+    if (p->nz < 1) return fail(RD_EINVAL, "nz = %d must be >= 1", p->nz);
+    if ((int64_t)p->nx * (int64_t)p->ny * (int64_t)p->nz >= ((int64_t)1 << 40))
+      return fail(RD_EINVAL, "grid %d x %d x %d has 2^40 cells or more", p->nx, p->ny, p->nz);
+  } else if (p->nz != 1) {
+    return fail(RD_EINVAL, "nz = %d: the 2-D stencils need nz = 1", p->nz);
+  }
   if (!(finite(p->dx) && p->dx > 0.0)) return fail(RD_EINVAL, "dx must be finite and > 0");
   if (!(finite(p->dt) && p->dt > 0.0)) return fail(RD_EINVAL, "dt must be finite and > 0");
   if (p->nsteps < 0) return fail(RD_EINVAL, "nsteps must be >= 0");
@@ -221,7 +228,8 @@ void set_geometry(KConst& c, int halo, int ty) {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t field_bytes(const rd_problem* p) {
-  return align_up((size_t)p->nx * (size_t)p->ny * sizeof(double), 256);
+  const size_t nz = is_3d(p->stencil) ? (size_t)p->nz : 1;
+  return align_up((size_t)p->nx * (size_t)p->ny * nz * sizeof(double), 256);
 }
 
 hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const SweepArgs& a,
@@ -405,6 +413,15 @@ int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out) {
   if (!out) return fail(RD_EINVAL, "out is NULL");
   const size_t nv = (size_t)n_fields(p->model);
   const size_t fb = field_bytes(p);
+  if (is_3d(p->stencil)) {
+    switch (op) {
+      case RD_OP_STEP: *out = workspace_3d(p, false); return RD_OK;
+      case RD_OP_JVP: *out = workspace_3d(p, true); return RD_OK;
+      case RD_OP_VJP:
+      case RD_OP_BATCHED: return fail(RD_EUNSUPPORTED, "the 3-D stencils support rd_step and rd_jvp only");
+    }
+    return fail(RD_EINVAL, "unknown op %d", op);
+  }
   switch (op) {
     case RD_OP_STEP: *out = nv * fb; return RD_OK;
     case RD_OP_JVP: return workspace_jvp(p, out);
@@ -429,11 +446,13 @@ int rd_step(const rd_problem* p, double* const* fields, double* checkpoints, voi
   rc = check_workspace(ws, ws_bytes, need);
   if (rc) return rc;
   const int nv = n_fields(p->model);
-  double* b[kMaxFields];
-  for (int f = 0; f < nv; ++f) b[f] = (double*)((char*)ws + f * field_bytes(p));
   hipStream_t s = (hipStream_t)hip_stream;
   KConst c;
   derive_constants(p, c);
+  if (is_3d(p->stencil))
+    return run_steps_3d(p, c, false, fields, (char*)ws, p->nsteps, checkpoints, p->checkpoint_every, s);
+  double* b[kMaxFields];
+  for (int f = 0; f < nv; ++f) b[f] = (double*)((char*)ws + f * field_bytes(p));
   plan_geometry(p, c, false, fields, b, s);
   return run_steps(p, c, false, fields, b, p->nsteps, checkpoints, p->checkpoint_every, s);
 }
@@ -452,7 +471,8 @@ int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents, 
       if (fields[i] == tangents[j]) return fail(RD_EINVAL, "fields[%d] aliases tangents[%d]", i, j);
   if (p->nsteps == 0) return RD_OK;
   size_t need = 0;
-  workspace_jvp(p, &need);
+  if (is_3d(p->stencil)) need = workspace_3d(p, true);
+  else workspace_jvp(p, &need);
   rc = check_workspace(ws, ws_bytes, need);
   if (rc) return rc;
   double* a[kMaxPacked];
@@ -465,6 +485,7 @@ int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents, 
   hipStream_t s = (hipStream_t)hip_stream;
   KConst c;
   derive_constants(p, c);
+  if (is_3d(p->stencil)) return run_steps_3d(p, c, true, a, (char*)ws, p->nsteps, nullptr, 0, s);
   plan_geometry(p, c, true, a, b, s);
   return run_steps(p, c, true, a, b, p->nsteps, nullptr, 0, s);
 }

@@ -24,6 +24,7 @@ static hipError_t launch_batch_kernel(bool tangent, int model, int stencil, int 
 // Everything except the grid size must agree across the batch.
 static int check_uniform(const rd_problem* probs, int32_t n) {
   const rd_problem& q = probs[0];
+  if (is_3d(q.stencil)) return fail(RD_EUNSUPPORTED, "batches of 3-D grids are not supported");
   for (int32_t i = 1; i < n; ++i) {
     const rd_problem& p = probs[i];
     const bool aniso = q.stencil == RD_LAP9_ANISO;
@@ -47,6 +48,7 @@ static int batch_workspace(const rd_problem* probs, int32_t n, bool tangent, siz
   for (int32_t i = 0; i < n; ++i) {
     int rc = validate(&probs[i]);
     if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
+    if (is_3d(probs[i].stencil)) return fail(RD_EUNSUPPORTED, "problem %d: batches of 3-D grids are not supported", i);
     total += (tangent ? 2 : 1) * (size_t)n_fields(probs[i].model) * field_bytes(&probs[i]);
   }
   *out = total;

@@ -50,6 +50,12 @@ size_t field_bytes(const rd_problem* p);
 int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hipStream_t s);
 
 int workspace_jvp(const rd_problem* p, size_t* out);
+
+// 3-D stencils (rd_api_3d.cpp).
+bool is_3d(int stencil);
+size_t workspace_3d(const rd_problem* p, bool tangent);
+int run_steps_3d(const rd_problem* p, const KConst& c, bool tangent, double* const* a, char* ws,
+                 int64_t nsteps, double* checkpoints, int every, hipStream_t s);
 int workspace_vjp(const rd_problem* p, size_t* out);
 
 }  // namespace rd

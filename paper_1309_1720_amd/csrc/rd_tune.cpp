@@ -217,6 +217,7 @@ int rd_set_kernel_variant(int32_t variant) {
 int rd_get_plan(const rd_problem* p, int32_t op, int32_t* variant, int32_t* rows) {
   int rc = rd::validate(p);
   if (rc) return rc;
+  if (rd::is_3d(p->stencil)) return rd::fail(RD_EUNSUPPORTED, "3-D grids have a fixed launch shape (no plan)");
   if (!rows || !variant) return rd::fail(RD_EINVAL, "output pointer is NULL");
   int kind;
   switch (op) {
@@ -235,6 +236,7 @@ int rd_get_plan(const rd_problem* p, int32_t op, int32_t* variant, int32_t* rows
 int rd_get_steps_per_launch(const rd_problem* p, int32_t* steps) {
   int rc = rd::validate(p);
   if (rc) return rc;
+  if (rd::is_3d(p->stencil)) return rd::fail(RD_EUNSUPPORTED, "3-D grids have a fixed launch shape (no plan)");
   if (!steps) return rd::fail(RD_EINVAL, "steps is NULL");
   const int ns = rd::n_stages(p->scheme);
   *steps = rd::current_plan(rd::kTuneForward, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true,
@@ -252,6 +254,7 @@ int rd_set_steps_per_launch(int32_t steps) {
 int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows) {
   int rc = rd::validate(p);
   if (rc) return rc;
+  if (rd::is_3d(p->stencil)) return rd::fail(RD_EUNSUPPORTED, "3-D grids have a fixed launch shape (no plan)");
   if (!rows) return rd::fail(RD_EINVAL, "rows is NULL");
   int kind;
   switch (op) {

@@ -26,7 +26,7 @@ from . import _binding as B
 
 
 def _views(flat: torch.Tensor, prob: B.Problem):
-    return list(flat.view(prob.nfields, prob.ny, prob.nx).unbind(0))
+    return list(flat.view(prob.nfields, *prob.shape).unbind(0))
 
 
 def _flat(fields) -> torch.Tensor:

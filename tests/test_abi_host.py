@@ -163,3 +163,31 @@ def test_gate_schemes_need_gated_models_and_no_adjoint():
     fake = (C.c_void_p * 3)(0x10000, 0x20000, 0x30000)
     rc = B.lib().rd_vjp(C.byref(cpf), 0x40000, fake, 0x100000, 1 << 30, None)
     assert rc == -2 and "Euler, Heun and RK4" in B.lib().rd_last_error().decode()
+
+
+def test_3d_problems_validated_before_any_device_work():
+    # nz must be 1 for the 2-D stencils and >= 1 for the 3-D ones
+    rc, msg = call_step(base_problem(nz=2))
+    assert rc == -1 and "nz" in msg
+    rc, msg = call_step(base_problem(stencil="lap19", nz=0))
+    assert rc == -1 and "nz" in msg
+    rc, msg = call_step(base_problem(stencil="lap27", nx=1 << 14, ny=1 << 14, nz=1 << 12))
+    assert rc == -1 and "2^40" in msg
+    # workspace: the ping-pong state plus NS - 1 stored rates, NV (or 2 NV) fields each
+    p = base_problem(stencil="lap27", nx=30, ny=20, nz=10)
+    fb = -(-30 * 20 * 10 * 8 // 256) * 256
+    assert rd.workspace_bytes(p, "step") == 4 * 3 * fb
+    assert rd.workspace_bytes(p, "jvp") == 4 * 6 * fb
+    p.scheme = "heun"
+    assert rd.workspace_bytes(p, "step") == 2 * 3 * fb
+    with pytest.raises(rd.RDError) as e:
+        rd.workspace_bytes(p, "vjp")
+    assert e.value.code == -2
+    cp, _b = p.to_c()
+    v, r = C.c_int32(), C.c_int32()
+    assert B.lib().rd_get_plan(C.byref(cp), 0, C.byref(v), C.byref(r)) == -2
+    p.checkpoint_every = 1
+    cp, _b = p.to_c()
+    fake = (C.c_void_p * 3)(1 << 16, 2 << 16, 3 << 16)
+    assert B.lib().rd_vjp(C.byref(cp), C.c_void_p(1 << 20), fake, C.c_void_p(1 << 24), 1 << 30, None) == -2
+    assert B.lib().rd_step_batched_workspace_bytes(C.byref(cp), 1, 0, C.byref(C.c_size_t())) == -2
