@@ -23,6 +23,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12           # bytes/s, MI355X HBM3E
+# Arrays streamed per field and cell by one RK4 step of the 3-D stage kernels:
+# stage 1 reads z, writes k1; stages 2 and 3 read z and k_{s-1}, write k_s;
+# stage 4 reads z, k1, k2, k3 and writes the new state: 2 + 3 + 3 + 5.
+STAGE3_RK4_FIELDS = 13
 FP64_VECTOR_PEAK = 78.6e12  # flop/s, MI355X FP64 vector (FMA = 2 flops)
 KERNEL_SOURCES = ["paper_1309_1720_amd/csrc/rd_device.h", "paper_1309_1720_amd/csrc/rd_sweep.h"]
 # Algorithmic FP64 operations per Fenton-Karma RK4 cell-update, counted from the
@@ -160,146 +164,170 @@ def _timed(torch, stream, fn, reps=1):
     return best
 
 
-def other_workloads(rd, torch, dev):
-    """Timings of the other workloads (rates in cell-updates/s, device time)."""
+def other_workloads(rd, torch, dev, only=None):
+    """Timings of the other workloads (rates in cell-updates/s, device time);
+    ``only`` names one of them to run alone."""
     import rd_inputs as ri
     stream = torch.cuda.current_stream(dev)
     out = {}
 
-    # Barkley 128^2, 5-point, Euler, 1000 steps (whole run)
-    w = ri.workload("barkley_128_euler")
-    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-    p = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=20)
-    rd.step(p, z)
-    p.nsteps = w["nsteps"]
-    sec = _timed(torch, stream, lambda: rd.step(p, z))
-    out["barkley_128_euler_1000"] = {"seconds": sec, "rate": 128 * 128 * w["nsteps"] / sec,
-                                     "steps_per_launch": rd.get_steps_per_launch(p),
-                                     "us_per_step": sec / w["nsteps"] * 1e6,
-                                     "hbm_frac": 32 * 128 * 128 * w["nsteps"] / sec / HBM_PEAK}
+    if only in (None, "barkley_128_euler_1000"):
+        # Barkley 128^2, 5-point, Euler, 1000 steps (whole run)
+        w = ri.workload("barkley_128_euler")
+        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+        p = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=20)
+        rd.step(p, z)
+        p.nsteps = w["nsteps"]
+        sec = _timed(torch, stream, lambda: rd.step(p, z))
+        out["barkley_128_euler_1000"] = {"seconds": sec, "rate": 128 * 128 * w["nsteps"] / sec,
+                                         "steps_per_launch": rd.get_steps_per_launch(p),
+                                         "us_per_step": sec / w["nsteps"] * 1e6,
+                                         "hbm_frac": 32 * 128 * 128 * w["nsteps"] / sec / HBM_PEAK}
 
-    # FitzHugh-Nagumo 256^2 (Eq. 3, u and v diffusive), 9-point, RK4, 1000 steps
-    w = ri.workload("fhn_256_rk4")
-    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-    p = rd.Problem.from_workload(w, ri.params_array("fhn"), nsteps=8)
-    rd.step(p, z)
-    p.nsteps = w["nsteps"]
-    sec = _timed(torch, stream, lambda: rd.step(p, z))
-    cells = w["nx"] * w["ny"]
-    out["fhn_256_rk4_1000"] = {"seconds": sec, "rate": cells * w["nsteps"] / sec,
-                               "us_per_step": sec / w["nsteps"] * 1e6,
-                               "steps_per_launch": rd.get_steps_per_launch(p),
-                               "plan": list(rd.get_plan(p, "step")),
-                               "hbm_frac": 32 * cells * w["nsteps"] / sec / HBM_PEAK}
+    if only in (None, "fhn_256_rk4_1000"):
+        # FitzHugh-Nagumo 256^2 (Eq. 3, u and v diffusive), 9-point, RK4, 1000 steps
+        w = ri.workload("fhn_256_rk4")
+        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+        p = rd.Problem.from_workload(w, ri.params_array("fhn"), nsteps=8)
+        rd.step(p, z)
+        p.nsteps = w["nsteps"]
+        sec = _timed(torch, stream, lambda: rd.step(p, z))
+        cells = w["nx"] * w["ny"]
+        out["fhn_256_rk4_1000"] = {"seconds": sec, "rate": cells * w["nsteps"] / sec,
+                                   "us_per_step": sec / w["nsteps"] * 1e6,
+                                   "steps_per_launch": rd.get_steps_per_launch(p),
+                                   "plan": list(rd.get_plan(p, "step")),
+                                   "hbm_frac": 32 * cells * w["nsteps"] / sec / HBM_PEAK}
 
-    # Bueno-Orovio 2048^2, anisotropic flux form, RK4 (50 of its 5000 steps)
-    w = ri.workload("bocf_2048_aniso_rk4")
-    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-    p = rd.Problem.from_workload(w, ri.params_array("bocf"), nsteps=4)
-    rd.step(p, z)
-    n = 50
-    p.nsteps = n
-    sec = _timed(torch, stream, lambda: rd.step(p, z))
-    cells = w["nx"] * w["ny"]
-    out["bocf_2048_aniso_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
-                                  "plan": list(rd.get_plan(p, "step")),
-                                  "hbm_frac": 64 * cells * n / sec / HBM_PEAK}
+    if only in (None, "bocf_2048_aniso_rk4"):
+        # Bueno-Orovio 2048^2, anisotropic flux form, RK4 (50 of its 5000 steps)
+        w = ri.workload("bocf_2048_aniso_rk4")
+        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+        p = rd.Problem.from_workload(w, ri.params_array("bocf"), nsteps=4)
+        rd.step(p, z)
+        n = 50
+        p.nsteps = n
+        sec = _timed(torch, stream, lambda: rd.step(p, z))
+        cells = w["nx"] * w["ny"]
+        out["bocf_2048_aniso_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
+                                      "plan": list(rd.get_plan(p, "step")),
+                                      "hbm_frac": 64 * cells * n / sec / HBM_PEAK}
 
-    # Beyond the 256 MB last-level cache: Fenton-Karma 4096^2 (3 x 128 MiB per
-    # state), the same scheme, so the traffic really goes to HBM.
-    w = ri.workload("fk_1024_rk4", nx=4096, ny=4096)
-    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-    p = rd.Problem.from_workload(w, ri.params_array("fk"), nsteps=2)
-    rd.step(p, z)
-    n = 20
-    p.nsteps = n
-    sec = _timed(torch, stream, lambda: rd.step(p, z))
-    cells = w["nx"] * w["ny"]
-    out["fk_4096_rk4_beyond_llc"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
-                                     "hbm_frac": 48 * cells * n / sec / HBM_PEAK,
-                                     "plan": list(rd.get_plan(p, "step"))}
-    del z
+    if only in (None, "fk_4096_rk4_beyond_llc"):
+        # Beyond the 256 MB last-level cache: Fenton-Karma 4096^2 (3 x 128 MiB per
+        # state), the same scheme, so the traffic really goes to HBM.
+        w = ri.workload("fk_1024_rk4", nx=4096, ny=4096)
+        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+        p = rd.Problem.from_workload(w, ri.params_array("fk"), nsteps=2)
+        rd.step(p, z)
+        n = 20
+        p.nsteps = n
+        sec = _timed(torch, stream, lambda: rd.step(p, z))
+        cells = w["nx"] * w["ny"]
+        out["fk_4096_rk4_beyond_llc"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
+                                         "hbm_frac": 48 * cells * n / sec / HBM_PEAK,
+                                         "plan": list(rd.get_plan(p, "step"))}
+        del z
 
-    # Ensemble: 64 Fenton-Karma grids (16 each of 256^2 .. 768^2) with tangents
-    ws = ri.fk_batch_workloads(nsteps=2)
-    params = ri.params_array("fk")
-    probs = [rd.Problem.from_workload(x, params) for x in ws]
-    fields = [[torch.from_numpy(a).to(dev) for a in ri.fk_ic(x["nx"], x["ny"], x["seed"])] for x in ws]
-    tans = [[torch.from_numpy(a).to(dev) for a in ri.direction(3, x["nx"], x["ny"], x["direction_seed"])]
-            for x in ws]
-    rd.step_batched(probs, fields, tans)      # first calls tune the band height
-    rd.step_batched(probs, fields, None)
-    for q, f, t in zip(probs, fields, tans):
-        rd.jvp(q, f, t)
-    torch.cuda.synchronize()
-    n = 20
-    for q in probs:
-        q.nsteps = n
-    cells = sum(x["nx"] * x["ny"] for x in ws)
-    sec_b = _timed(torch, stream, lambda: rd.step_batched(probs, fields, tans), reps=3)
-    sec_f = _timed(torch, stream, lambda: rd.step_batched(probs, fields, None), reps=3)
-
-    def per_instance():
+    if only in (None, "fk_ensemble_64_jvp"):
+        # Ensemble: 64 Fenton-Karma grids (16 each of 256^2 .. 768^2) with tangents
+        ws = ri.fk_batch_workloads(nsteps=2)
+        params = ri.params_array("fk")
+        probs = [rd.Problem.from_workload(x, params) for x in ws]
+        fields = [[torch.from_numpy(a).to(dev) for a in ri.fk_ic(x["nx"], x["ny"], x["seed"])] for x in ws]
+        tans = [[torch.from_numpy(a).to(dev) for a in ri.direction(3, x["nx"], x["ny"], x["direction_seed"])]
+                for x in ws]
+        rd.step_batched(probs, fields, tans)      # first calls tune the band height
+        rd.step_batched(probs, fields, None)
         for q, f, t in zip(probs, fields, tans):
             rd.jvp(q, f, t)
-    sec_s = _timed(torch, stream, per_instance, reps=3)
-    # the same batched call captured once in a HIP graph and replayed
-    gstream = torch.cuda.Stream(dev)
-    gstream.wait_stream(stream)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(gstream):
-        with torch.cuda.graph(graph, stream=gstream):
-            rd.step_batched(probs, fields, tans)
-    stream.wait_stream(gstream)
-    sec_g = _timed(torch, stream, graph.replay, reps=3)
-    out["fk_ensemble_64_jvp"] = {"steps": n, "cells": cells, "rate_jvp": cells * n / sec_b,
-                                 "rate_forward": cells * n / sec_f, "jvp_over_forward": sec_b / sec_f,
-                                 "per_instance_calls_over_batched": sec_s / sec_b,
-                                 "rate_jvp_graph_replay": cells * n / sec_g,
-                                 "hbm_frac_jvp": 96 * cells * n / sec_b / HBM_PEAK}
-
-    # Newton-Krylov fixed points of the 200-step FitzHugh-Nagumo flow for a
-    # small ensemble (stable and unstable uniform states), exact vs FD JVPs
-    import numpy as np
-    from paper_1309_1720_amd import krylov
-    fp = ri.FHN_PARAMS
-    roots = sorted(r.real for r in np.roots([1.0, 0.0, -(1.0 - 1.0 / fp["a1"]), -fp["a0"] / fp["a1"]])
-                   if abs(r.imag) < 1e-12)
-    members = []
-    for (nx, ny), u in (((96, 80), roots[0]), ((128, 96), roots[2]), ((160, 128), roots[0])):
-        wk = ri.workload("fhn_256_rk4", nx=nx, ny=ny, nsteps=200)
-        i = np.arange(nx)[None, :]
-        j = np.arange(ny)[:, None]
-        pat = np.cos(np.pi * (i + 0.5) / nx) * np.cos(2 * np.pi * (j + 0.5) / ny)
-        v = (u - fp["a0"]) / fp["a1"]
-        members.append((rd.Problem.from_workload(wk, ri.params_array("fhn")),
-                        [torch.from_numpy(u + 0.01 * pat).to(dev), torch.from_numpy(v + 0.02 * pat).to(dev)]))
-    nk = {}
-    for kind in ("exact", "fd"):
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = krylov.newton_krylov([m[0] for m in members], [m[1] for m in members], tol=1e-13,
-                                   max_newton=8, jvp=kind)
-        torch.cuda.synchronize()
-        nk[kind] = {"seconds": time.perf_counter() - t0, "residuals": res.residuals,
-                    "krylov_iterations": res.krylov_iterations}
-    out["newton_krylov_fhn_3_members_200_steps"] = nk
+        n = 20
+        for q in probs:
+            q.nsteps = n
+        cells = sum(x["nx"] * x["ny"] for x in ws)
+        sec_b = _timed(torch, stream, lambda: rd.step_batched(probs, fields, tans), reps=3)
+        sec_f = _timed(torch, stream, lambda: rd.step_batched(probs, fields, None), reps=3)
 
-    # Adjoint: Barkley 1024^2, RK4, 4000 steps, checkpoints every 64
-    w = ri.workload("barkley_1024_rk4_adjoint")
-    p = rd.Problem.from_workload(w, ri.params_array("barkley"))
-    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-    ck = torch.empty(rd.checkpoint_count(p) * 2 * w["nx"] * w["ny"], dtype=torch.float64, device=dev)
-    warm = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=2)
-    rd.step(warm, [t.clone() for t in z])   # tunes the forward plan outside the timed region
-    sec_fwd = _timed(torch, stream, lambda: rd.step(p, z, ck))
-    lam = [(2.0 * w["dx"] ** 2) * z[0].clone(), torch.zeros_like(z[1])]
-    sec_vjp = _timed(torch, stream, lambda: rd.vjp(p, ck, lam))
-    cells = w["nx"] * w["ny"]
-    out["barkley_1024_rk4_adjoint_4000"] = {
-        "forward_seconds": sec_fwd, "vjp_seconds": sec_vjp, "vjp_over_forward": sec_vjp / sec_fwd,
-        "forward_rate": cells * w["nsteps"] / sec_fwd, "forward_steps_per_launch": rd.get_steps_per_launch(p),
-        "forward_hbm_frac": 32 * cells * w["nsteps"] / sec_fwd / HBM_PEAK}
+        def per_instance():
+            for q, f, t in zip(probs, fields, tans):
+                rd.jvp(q, f, t)
+        sec_s = _timed(torch, stream, per_instance, reps=3)
+        # the same batched call captured once in a HIP graph and replayed
+        gstream = torch.cuda.Stream(dev)
+        gstream.wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(gstream):
+            with torch.cuda.graph(graph, stream=gstream):
+                rd.step_batched(probs, fields, tans)
+        stream.wait_stream(gstream)
+        sec_g = _timed(torch, stream, graph.replay, reps=3)
+        out["fk_ensemble_64_jvp"] = {"steps": n, "cells": cells, "rate_jvp": cells * n / sec_b,
+                                     "rate_forward": cells * n / sec_f, "jvp_over_forward": sec_b / sec_f,
+                                     "per_instance_calls_over_batched": sec_s / sec_b,
+                                     "rate_jvp_graph_replay": cells * n / sec_g,
+                                     "hbm_frac_jvp": 96 * cells * n / sec_b / HBM_PEAK}
+
+    if only in (None, "newton_krylov_fhn_3_members_200_steps"):
+        # Newton-Krylov fixed points of the 200-step FitzHugh-Nagumo flow for a
+        # small ensemble (stable and unstable uniform states), exact vs FD JVPs
+        import numpy as np
+        from paper_1309_1720_amd import krylov
+        fp = ri.FHN_PARAMS
+        roots = sorted(r.real for r in np.roots([1.0, 0.0, -(1.0 - 1.0 / fp["a1"]), -fp["a0"] / fp["a1"]])
+                       if abs(r.imag) < 1e-12)
+        members = []
+        for (nx, ny), u in (((96, 80), roots[0]), ((128, 96), roots[2]), ((160, 128), roots[0])):
+            wk = ri.workload("fhn_256_rk4", nx=nx, ny=ny, nsteps=200)
+            i = np.arange(nx)[None, :]
+            j = np.arange(ny)[:, None]
+            pat = np.cos(np.pi * (i + 0.5) / nx) * np.cos(2 * np.pi * (j + 0.5) / ny)
+            v = (u - fp["a0"]) / fp["a1"]
+            members.append((rd.Problem.from_workload(wk, ri.params_array("fhn")),
+                            [torch.from_numpy(u + 0.01 * pat).to(dev), torch.from_numpy(v + 0.02 * pat).to(dev)]))
+        nk = {}
+        for kind in ("exact", "fd"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = krylov.newton_krylov([m[0] for m in members], [m[1] for m in members], tol=1e-13,
+                                       max_newton=8, jvp=kind)
+            torch.cuda.synchronize()
+            nk[kind] = {"seconds": time.perf_counter() - t0, "residuals": res.residuals,
+                        "krylov_iterations": res.krylov_iterations}
+        out["newton_krylov_fhn_3_members_200_steps"] = nk
+
+    if only in (None, "fk_256cube_lap27_rk4"):
+        # 3-D: Fenton-Karma 256^3, 27-point, RK4 (20 of its 1000 steps), one
+        # HBM-bound launch per stage (STAGE3_RK4_FIELDS arrays per field and cell).
+        w = ri.workload("fk_256cube_lap27_rk4")
+        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+        p = rd.Problem.from_workload(w, ri.params_array("fk"), nsteps=2)
+        rd.step(p, z)
+        n = 20
+        p.nsteps = n
+        sec = _timed(torch, stream, lambda: rd.step(p, z), reps=2)
+        cells = w["nx"] * w["ny"] * w["nz"]
+        out["fk_256cube_lap27_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
+                                       "hbm_bytes_per_cell_update": STAGE3_RK4_FIELDS * 3 * 8,
+                                       "hbm_frac": STAGE3_RK4_FIELDS * 3 * 8 * cells * n / sec / HBM_PEAK}
+        del z
+
+    if only in (None, "barkley_1024_rk4_adjoint_4000"):
+        # Adjoint: Barkley 1024^2, RK4, 4000 steps, checkpoints every 64
+        w = ri.workload("barkley_1024_rk4_adjoint")
+        p = rd.Problem.from_workload(w, ri.params_array("barkley"))
+        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+        ck = torch.empty(rd.checkpoint_count(p) * 2 * w["nx"] * w["ny"], dtype=torch.float64, device=dev)
+        warm = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=2)
+        rd.step(warm, [t.clone() for t in z])   # tunes the forward plan outside the timed region
+        sec_fwd = _timed(torch, stream, lambda: rd.step(p, z, ck))
+        lam = [(2.0 * w["dx"] ** 2) * z[0].clone(), torch.zeros_like(z[1])]
+        sec_vjp = _timed(torch, stream, lambda: rd.vjp(p, ck, lam))
+        cells = w["nx"] * w["ny"]
+        out["barkley_1024_rk4_adjoint_4000"] = {
+            "forward_seconds": sec_fwd, "vjp_seconds": sec_vjp, "vjp_over_forward": sec_vjp / sec_fwd,
+            "forward_rate": cells * w["nsteps"] / sec_fwd, "forward_steps_per_launch": rd.get_steps_per_launch(p),
+            "forward_hbm_frac": 32 * cells * w["nsteps"] / sec_fwd / HBM_PEAK}
     return out
 
 
@@ -314,6 +342,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jvp", action="store_true")
     ap.add_argument("--no-other-workloads", action="store_true")
+    ap.add_argument("--only-workload", default=None,
+                    help="run only this one of the other workloads and print its record")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -333,6 +363,12 @@ def main():
     nv = ri.N_FIELDS["fk"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only_workload:
+        rec = other_workloads(rd, torch, dev, only=args.only_workload)
+        if not rec:
+            raise SystemExit(f"bench.py: unknown workload {args.only_workload!r}")
+        print(json.dumps(rec))
+        return
     z0_np = ri.initial_condition(w)
     z = [torch.from_numpy(a).to(dev) for a in z0_np]
     if args.tile_rows:

@@ -10,7 +10,7 @@ namespace rd {
 
 bool is_3d(int stencil) { return stencil == RD_LAP7 || stencil == RD_LAP19 || stencil == RD_LAP27; }
 
-// Workgroup grid: 62-column strips x groups of four rows x chunks of zc
+// Workgroup grid: 64-column strips x groups of four rows x chunks of zc
 // planes, with enough chunks for about 8192 wavefronts (32 per CU) and at
 // least four planes per chunk (each chunk reads two extra planes).
 static void geometry_3d(const rd_problem* p, Stage3Args& a) {

@@ -13,9 +13,13 @@
 // and much simpler.  Each launch is HBM-bound.
 //
 // Geometry.  A workgroup is four wavefronts; wavefront w holds row y0 + w of
-// a 62-column strip (lanes 0 and 63 are halo lanes, the x-neighbours come
-// from the adjacent lanes through DPP) and marches through a chunk of zc
-// planes.  Per plane and diffusive component it loads rows y - 1, y, y + 1
+// a 64-column strip aligned to 64 columns (every lane an output; the
+// x-neighbours come from the adjacent lanes through DPP, and lanes 0 and 63
+// fetch the one column beyond each end of the strip in an extra load) and
+// marches through a chunk of zc planes.  Aligned strips keep every row
+// access and every store on whole cache lines; strips with halo lanes
+// (62 outputs starting one column early) split each access across an extra
+// line and were measured about 25% slower.  Per plane and diffusive component it loads rows y - 1, y, y + 1
 // and forms three aggregates: U (the cell), F (its four in-plane face
 // neighbours) and G (its four in-plane diagonals).  A register ring keeps
 // them for planes z - 1, z, z + 1, from which the 26-neighbour groups follow:
@@ -32,7 +36,7 @@
 namespace rd {
 
 constexpr int kStage3Waves = 4;              // rows (wavefronts) per workgroup
-constexpr int kStage3Width = kWave - 2;      // output columns per wavefront
+constexpr int kStage3Width = kWave;          // output columns per wavefront
 constexpr int kMaxPacked3 = 2 * kMaxFields;  // state fields, then tangent fields
 
 // 3-D stencil weights (faces, edges, corners); see include/rd.h.
@@ -84,18 +88,34 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void stage3d_kernel(Stage3Args
   const int lane = threadIdx.x & (kWave - 1);
   const int gy = by * kStage3Waves + (int)(threadIdx.x >> 6);
   if (gy >= c.ny) return;  // whole wavefront
-  const int gx = bx * kStage3Width - 1 + lane;
-  const bool out_col = lane >= 1 && lane <= kStage3Width && gx < c.nx;
+  const int gx = bx * kStage3Width + lane;
+  const bool out_col = gx < c.nx;
+  const bool edge = lane == 0 || lane == kWave - 1;
+  // lane 0 fetches the column west of the strip, lane 63 the one east of it
+  const size_t hx = (size_t)grid_index(lane == 0 ? bx * kStage3Width - 1 : bx * kStage3Width + kWave, c.nx, c);
   const size_t nx = (size_t)c.nx;
   const size_t plane = nx * (size_t)c.ny;
   const size_t cx = (size_t)grid_index(gx, c.nx, c);
   const size_t rC = (size_t)gy * nx + cx;
   const size_t rN = (size_t)grid_index(gy - 1, c.ny, c) * nx + cx;
   const size_t rS = (size_t)grid_index(gy + 1, c.ny, c) * nx + cx;
+  const size_t hC = (size_t)gy * nx + hx;
+  const size_t hN = (size_t)grid_index(gy - 1, c.ny, c) * nx + hx;
+  const size_t hS = (size_t)grid_index(gy + 1, c.ny, c) * nx + hx;
 
   auto yval = [&](int f, size_t o) -> double {
     if constexpr (HASKP) return a.z[f][o] + a.a_in * a.kp[f][o];
     return a.z[f][o];
+  };
+
+  // x-neighbours: the adjacent lane's value, or the fetched one past the strip
+  auto west = [&](double v, double h) {
+    const double w = from_west(v);
+    return lane == 0 ? h : w;
+  };
+  auto east = [&](double v, double h) {
+    const double e = from_east(v);
+    return lane == kWave - 1 ? h : e;
   };
 
   // ring slot 0/1/2 = planes z-1, z, z+1
@@ -106,9 +126,15 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void stage3d_kernel(Stage3Args
     for (int d = 0; d < ND; ++d) {
       const int f = comp(d);
       const double yc = yval(f, base + rC), yn = yval(f, base + rN), ys = yval(f, base + rS);
+      double hc = 0.0, hn = 0.0, hs = 0.0;
+      if (edge) {
+        hc = yval(f, base + hC);
+        hn = yval(f, base + hN);
+        hs = yval(f, base + hS);
+      }
       U[slot][d] = yc;
-      F[slot][d] = (from_west(yc) + from_east(yc)) + (yn + ys);
-      if constexpr (DIAG) G[slot][d] = (from_west(yn) + from_east(yn)) + (from_west(ys) + from_east(ys));
+      F[slot][d] = (west(yc, hc) + east(yc, hc)) + (yn + ys);
+      if constexpr (DIAG) G[slot][d] = (west(yn, hn) + east(yn, hn)) + (west(ys, hs) + east(ys, hs));
     }
   };
 

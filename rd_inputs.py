@@ -113,7 +113,7 @@ def workload(name: str, **overrides) -> dict:
     return w
 
 
-_BASE = dict(D_perp=None, theta0=0.0, theta1=0.0, step_k=STEP_K, checkpoint_every=0, bc="noflux")
+_BASE = dict(D_perp=None, theta0=0.0, theta1=0.0, step_k=STEP_K, checkpoint_every=0, bc="noflux", nz=1)
 
 _WORKLOADS = {
     # Barkley 128x128, 5-point Laplacian, forward Euler, 1000 steps.
@@ -142,6 +142,12 @@ _WORKLOADS = {
                                      nx=1024, ny=1024, dx=0.5, dt=0.02, nsteps=4000,
                                      D_par=1.0, ic="barkley", seed=5,
                                      checkpoint_every=64),
+    # Fenton-Karma on a 256^3 block (3-D tissue, which the conclusion looks
+    # ahead to), compact 27-point operator, RK4; the 2-D workload's spacing
+    # and step, a scroll-wave seed (the broken-wave seed extruded along z).
+    "fk_256cube_lap27_rk4": dict(_BASE, model="fk", stencil="lap27", scheme="rk4",
+                                 nx=256, ny=256, nz=256, dx=0.025, dt=0.1, nsteps=1000,
+                                 D_par=0.001, ic="fk3d", seed=7),
 }
 
 # Ensemble of Fenton-Karma instances on uneven grids, tangent-linear run:
@@ -212,6 +218,13 @@ def fk_ic(nx: int, ny: int, seed: int, amp: float = 1e-4) -> list[np.ndarray]:
     return _noise(rng, [u, v, w], amp)
 
 
+def fk_ic3(nx: int, ny: int, nz: int, seed: int, amp: float = 1e-4) -> list[np.ndarray]:
+    """Scroll-wave seed: the 2-D broken-wave seed on every plane, plus noise."""
+    u, v, w, _, _ = _fk_pattern(nx, ny)
+    rng = np.random.default_rng(seed)
+    return _noise(rng, [np.repeat(f[None], nz, axis=0) for f in (u, v, w)], amp)
+
+
 def bocf_ic(nx: int, ny: int, seed: int, amp: float = 1e-4, blocks: int = 4) -> list[np.ndarray]:
     """Multi-spiral seed: a blocks x blocks grid of broken-wave seeds, each
     rotated (square blocks) or flipped by a seeded multiple of 90 degrees."""
@@ -269,6 +282,8 @@ def initial_condition(w: dict) -> list[np.ndarray]:
         return barkley_ic(w["nx"], w["ny"], w["seed"])
     if kind == "fk":
         return fk_ic(w["nx"], w["ny"], w["seed"])
+    if kind == "fk3d":
+        return fk_ic3(w["nx"], w["ny"], w["nz"], w["seed"])
     if kind == "bocf":
         return bocf_ic(w["nx"], w["ny"], w["seed"])
     if kind == "diffusion":
