@@ -307,10 +307,19 @@ def other_workloads(rd, torch, dev, only=None):
         p.nsteps = n
         sec = _timed(torch, stream, lambda: rd.step(p, z), reps=2)
         cells = w["nx"] * w["ny"] * w["nz"]
+        # adjoint over the same 20 steps, checkpoints every 10
+        p.checkpoint_every = 10
+        ck = torch.empty(rd.checkpoint_count(p) * 3 * cells, dtype=torch.float64, device=dev)
+        sec_ck = _timed(torch, stream, lambda: rd.step(p, z, ck))
+        lam = [t.clone() for t in z]
+        rd.vjp(p, ck, [t.clone() for t in z])
+        sec_vjp = _timed(torch, stream, lambda: rd.vjp(p, ck, lam))
         out["fk_256cube_lap27_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
                                        "hbm_bytes_per_cell_update": STAGE3_RK4_FIELDS * 3 * 8,
-                                       "hbm_frac": STAGE3_RK4_FIELDS * 3 * 8 * cells * n / sec / HBM_PEAK}
-        del z
+                                       "hbm_frac": STAGE3_RK4_FIELDS * 3 * 8 * cells * n / sec / HBM_PEAK,
+                                       "vjp_us_per_step": sec_vjp / n * 1e6,
+                                       "vjp_over_forward_with_checkpoints": sec_vjp / sec_ck}
+        del z, ck, lam
 
     if only in (None, "barkley_1024_rk4_adjoint_4000"):
         # Adjoint: Barkley 1024^2, RK4, 4000 steps, checkpoints every 64

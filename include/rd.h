@@ -103,8 +103,9 @@ enum rd_scheme {
  *   RD_LAP27  w = (7/15, 1/10, 1/30)  isotropic leading error, compact
  * Both isotropic members reduce to Eq. (6) on a single plane with mirrored
  * z-neighbours, as RD_LAP7 reduces to RD_LAP5.  Boundaries as in 2-D, in all
- * three directions.  rd_step and rd_jvp take them (every model and scheme);
- * rd_vjp and rd_step_batched return RD_EUNSUPPORTED. */
+ * three directions.  rd_step and rd_jvp take them (every model and scheme),
+ * rd_vjp too (every model; Euler, Heun, RK4); rd_step_batched returns
+ * RD_EUNSUPPORTED. */
 enum rd_stencil {
   RD_LAP5 = 5, RD_LAP9 = 9, RD_LAP9_ANISO = 10,
   RD_LAP7 = 7, RD_LAP19 = 19, RD_LAP27 = 27

@@ -417,8 +417,8 @@ int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out) {
     switch (op) {
       case RD_OP_STEP: *out = workspace_3d(p, false); return RD_OK;
       case RD_OP_JVP: *out = workspace_3d(p, true); return RD_OK;
-      case RD_OP_VJP:
-      case RD_OP_BATCHED: return fail(RD_EUNSUPPORTED, "the 3-D stencils support rd_step and rd_jvp only");
+      case RD_OP_VJP: *out = workspace_vjp_3d(p); return RD_OK;
+      case RD_OP_BATCHED: return fail(RD_EUNSUPPORTED, "batches of 3-D grids are not supported");
     }
     return fail(RD_EINVAL, "unknown op %d", op);
   }

@@ -29,7 +29,7 @@ static size_t vjp_arrays(const rd_problem* p) {
 }
 
 int workspace_vjp(const rd_problem* p, size_t* out) {
-  *out = vjp_arrays(p) * field_bytes(p);
+  *out = is_3d(p->stencil) ? workspace_vjp_3d(p) : vjp_arrays(p) * field_bytes(p);
   return RD_OK;
 }
 
@@ -45,7 +45,6 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
   if (rc) return rc;
   if (gate_scheme(p->scheme))
     return fail(RD_EUNSUPPORTED, "rd_vjp supports the Euler, Heun and RK4 schemes");
-  if (is_3d(p->stencil)) return fail(RD_EUNSUPPORTED, "rd_vjp does not support the 3-D stencils");
   if (p->checkpoint_every <= 0) return fail(RD_EINVAL, "rd_vjp needs checkpoint_every > 0");
   if (p->nsteps == 0) return RD_OK;
   if (!checkpoints) return fail(RD_EINVAL, "checkpoints is NULL");
@@ -56,6 +55,11 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
     return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
   if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
 
+  if (is_3d(p->stencil)) {
+    KConst c3;
+    derive_constants(p, c3);
+    return vjp_3d(p, c3, checkpoints, cot, (char*)ws, (hipStream_t)hip_stream);
+  }
   const int nv = n_fields(p->model);
   const int ns = n_stages(p->scheme);
   const int C = p->checkpoint_every;

@@ -56,6 +56,9 @@ bool is_3d(int stencil);
 size_t workspace_3d(const rd_problem* p, bool tangent);
 int run_steps_3d(const rd_problem* p, const KConst& c, bool tangent, double* const* a, char* ws,
                  int64_t nsteps, double* checkpoints, int every, hipStream_t s);
+size_t workspace_vjp_3d(const rd_problem* p);
+int vjp_3d(const rd_problem* p, const KConst& c, const double* checkpoints, double* const* cot, char* ws,
+           hipStream_t s);
 int workspace_vjp(const rd_problem* p, size_t* out);
 
 }  // namespace rd

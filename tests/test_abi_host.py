@@ -180,14 +180,18 @@ def test_3d_problems_validated_before_any_device_work():
     assert rd.workspace_bytes(p, "jvp") == 4 * 6 * fb
     p.scheme = "heun"
     assert rd.workspace_bytes(p, "step") == 2 * 3 * fb
-    with pytest.raises(rd.RDError) as e:
-        rd.workspace_bytes(p, "vjp")
-    assert e.value.code == -2
+    # adjoint: (C - 1) states, NS - 1 rates, two Ybar buffers, zbar and the cotangent partner
+    p.checkpoint_every = 5
+    assert rd.workspace_bytes(p, "vjp") == 3 * (4 + 1 + 4) * fb
     cp, _b = p.to_c()
     v, r = C.c_int32(), C.c_int32()
     assert B.lib().rd_get_plan(C.byref(cp), 0, C.byref(v), C.byref(r)) == -2
-    p.checkpoint_every = 1
-    cp, _b = p.to_c()
-    fake = (C.c_void_p * 3)(1 << 16, 2 << 16, 3 << 16)
-    assert B.lib().rd_vjp(C.byref(cp), C.c_void_p(1 << 20), fake, C.c_void_p(1 << 24), 1 << 30, None) == -2
     assert B.lib().rd_step_batched_workspace_bytes(C.byref(cp), 1, 0, C.byref(C.c_size_t())) == -2
+    # rejected before any launch: no checkpoint spacing, a gate scheme
+    fake = (C.c_void_p * 3)(1 << 16, 2 << 16, 3 << 16)
+    for kw in ({"checkpoint_every": 0}, {"scheme": "rush_larsen"}):
+        q = base_problem(stencil="lap27", nx=30, ny=20, nz=10, checkpoint_every=5)
+        for k, val in kw.items():
+            setattr(q, k, val)
+        cq, _bq = q.to_c()
+        assert B.lib().rd_vjp(C.byref(cq), C.c_void_p(1 << 20), fake, C.c_void_p(1 << 24), 1 << 30, None) in (-1, -2)

@@ -1,4 +1,4 @@
-"""GPU parity of the 3-D stencils (rd_step, rd_jvp with RD_LAP7/19/27)
+"""GPU parity of the 3-D stencils (rd_step, rd_jvp, rd_vjp with RD_LAP7/19/27)
 against the oracle, through the C ABI, plus properties that hold at any
 size: the reduction of a single plane to the 2-D operators, z-invariance,
 translation equivariance, a Fourier eigenmode at 256^3, checkpoints and HIP
@@ -198,10 +198,54 @@ def test_3d_step_graph_replays():
         assert all(np.array_equal(a, b) for a, b in zip(host(z), host(zr))), rep
 
 
-def test_3d_unsupported_operations_raise():
-    _, pr, z0 = setup("fk", "lap19", "rk4", 20, 8, 5, 2, checkpoint_every=1)
-    with pytest.raises(rd.RDError):
-        ck = torch.zeros(2 * 3 * pr.cells, dtype=torch.float64, device="cuda")
-        rd.vjp(pr, ck, dev(z0))
+def test_3d_batches_are_rejected():
+    _, pr, z0 = setup("fk", "lap19", "rk4", 20, 8, 5, 2)
     with pytest.raises(rd.RDError):
         rd.step_batched([pr], [dev(z0)])
+
+
+def gpu_vjp(pr, z0, lam):
+    zt = dev(z0)
+    ck = torch.zeros(max(rd.checkpoint_count(pr), 1) * pr.nfields * pr.cells, dtype=torch.float64, device="cuda")
+    rd.step(pr, zt, ck)
+    lt = dev(lam)
+    rd.vjp(pr, ck, lt)
+    return host(lt)
+
+
+@pytest.mark.parametrize("model,stencil,scheme", list(itertools.product(MODELS, ST3, ["euler", "heun", "rk4"])))
+def test_3d_vjp_matches_oracle(model, stencil, scheme):
+    """20 x 9 x 6 (a ragged strip, row groups and z chunks), 5 steps,
+    checkpoints every 2 (a ragged last segment)."""
+    po, pr, z0 = setup(model, stencil, scheme, 20, 9, 6, 5, checkpoint_every=2)
+    lam = ri.direction(len(z0), 20, 9, 21, nz=6)
+    ref = oracle.vjp(po, z0, lam, 5, checkpoint_every=2)
+    got = gpu_vjp(pr, z0, lam)
+    err = rel_linf(got, ref)
+    print(f"3-D {model} {stencil} {scheme}: adjoint rel-Linf {err:.3e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("model,stencil,bc", [("fk", "lap27", "periodic"), ("fhn", "lap19", "noflux"),
+                                              ("bocf", "lap7", "periodic")])
+def test_3d_vjp_periodic_and_degenerate(model, stencil, bc):
+    for nx, ny, nz in ((1, 1, 1), (9, 1, 2), (66, 5, 3)):
+        po, pr, z0 = setup(model, stencil, "rk4", nx, ny, nz, 3, bc=bc, checkpoint_every=2)
+        lam = ri.direction(len(z0), nx, ny, 5, nz=nz)
+        ref = oracle.vjp(po, z0, lam, 3, checkpoint_every=2)
+        assert rel_linf(gpu_vjp(pr, z0, lam), ref) <= TOL, (nx, ny, nz)
+
+
+@pytest.mark.parametrize("model,stencil,bc", [("fk", "lap27", "noflux"), ("bocf", "lap19", "periodic"),
+                                              ("fhn", "lap7", "noflux"), ("barkley", "lap27", "periodic")])
+def test_3d_dot_product(model, stencil, bc):
+    """<lambda, J v> = <J^T lambda, v> for the GPU tangent and adjoint on 70 x 21 x 13, 12 RK4 steps."""
+    nx, ny, nz = 70, 21, 13
+    _, pr, z0 = setup(model, stencil, "rk4", nx, ny, nz, 12, bc=bc, checkpoint_every=5)
+    v = ri.direction(len(z0), nx, ny, 1, nz=nz)
+    lam = ri.direction(len(z0), nx, ny, 2, nz=nz)
+    _, jv = gpu_jvp(pr, z0, v)
+    jtl = gpu_vjp(pr, z0, lam)
+    lhs = sum(float(np.sum(a * b)) for a, b in zip(lam, jv))
+    rhs = sum(float(np.sum(a * b)) for a, b in zip(jtl, v))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
