@@ -249,3 +249,16 @@ def test_3d_dot_product(model, stencil, bc):
     lhs = sum(float(np.sum(a * b)) for a, b in zip(lam, jv))
     rhs = sum(float(np.sum(a * b)) for a, b in zip(jtl, v))
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs))
+
+
+def test_3d_autograd_flow_gradient():
+    """torch.autograd through rd.flow on a 3-D problem: the gradient of
+    L = sum(u(T)^2) equals the oracle's adjoint of 2 u(T)."""
+    po, pr, z0 = setup("fhn", "lap19", "rk4", 30, 10, 6, 7, checkpoint_every=3)
+    zs = [t.requires_grad_(True) for t in dev(z0)]
+    out = rd.flow(pr, *zs)
+    loss = (out[0] * out[0]).sum()
+    loss.backward()
+    zT = oracle.step(po, z0, 7)
+    ref = oracle.vjp(po, z0, [2.0 * zT[0], np.zeros_like(zT[1])], 7, checkpoint_every=3)
+    assert rel_linf([t.grad.cpu().numpy() for t in zs], ref) <= TOL
