@@ -128,8 +128,8 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void adjoint3d_kernel(Adj3Args
 #pragma unroll
       for (int f = 0; f < NV; ++f) {
         const double zs = a.zs_in[f][o];
-        a.zs_out[f][o] = zs + yb[f];
-        if constexpr (WRITEYB) a.yb_out[f][o] = yb[f];
+        __builtin_nontemporal_store(zs + yb[f], &a.zs_out[f][o]);
+        if constexpr (WRITEYB) __builtin_nontemporal_store(yb[f], &a.yb_out[f][o]);
       }
     }
 #pragma unroll
