@@ -690,3 +690,112 @@ def test_periodic_conserves_sum_and_commutes_with_shifts(stencil):
     assert abs(out.sum() - u.sum()) <= 1e-13 * u.sum()
     shifted = oracle.step(p, [np.roll(np.roll(u, 3, axis=1), -2, axis=0)], 50)[0]
     assert np.allclose(shifted, np.roll(np.roll(out, 3, axis=1), -2, axis=0), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Brute force and precision floor
+# ---------------------------------------------------------------------------
+
+def _brute_step(p, z, nsteps):
+    """The explicit schemes of Sect. 3 as scalar loops over a tiny grid: the
+    ghost rule of Fig. 1 (or the periodic wrap) by explicit index
+    arithmetic, the 5-point or Eq. (6) 9-point sums neighbour by neighbour,
+    and the reaction evaluated one cell at a time."""
+    ny, nx = p.ny, p.nx
+    periodic = p.bc == "periodic"
+    diff = [(0, 1.0)] + ([(1, p.params[0])] if p.model == "fhn" else [])
+
+    def at(a, j, i):
+        if periodic:
+            return a[j % ny][i % nx]
+        return a[min(max(j, 0), ny - 1)][min(max(i, 0), nx - 1)]
+
+    def lap(a, j, i, c):
+        axial = at(a, j, i - 1) + at(a, j, i + 1) + at(a, j - 1, i) + at(a, j + 1, i) - 4.0 * a[j][i]
+        if p.stencil == "lap5":
+            return c * axial
+        diag = at(a, j - 1, i - 1) + at(a, j - 1, i + 1) + at(a, j + 1, i - 1) + at(a, j + 1, i + 1) - 4.0 * a[j][i]
+        return c * (2.0 / 3.0 * axial + 1.0 / 6.0 * diag)
+
+    def f(y):
+        nv = len(y)
+        out = [[[0.0] * nx for _ in range(ny)] for _ in range(nv)]
+        for j in range(ny):
+            for i in range(nx):
+                cell = oracle.reaction(p, [np.array([[y[m][j][i]]]) for m in range(nv)])
+                for m in range(nv):
+                    out[m][j][i] = float(cell[m][0, 0])
+                for m, rel in diff:
+                    out[m][j][i] += lap(y[m], j, i, p.D_par * rel / (p.dx * p.dx))
+        return out
+
+    def axpy(y, a, k):
+        return [[[y[m][j][i] + a * k[m][j][i] for i in range(nx)] for j in range(ny)] for m in range(len(y))]
+
+    y = [[[float(v) for v in row] for row in a] for a in z]
+    dt = p.dt
+    for _ in range(nsteps):
+        if p.scheme == "euler":
+            y = axpy(y, dt, f(y))
+        elif p.scheme == "heun":
+            k1 = f(y)
+            k2 = f(axpy(y, dt, k1))
+            y = [[[y[m][j][i] + dt / 2 * (k1[m][j][i] + k2[m][j][i]) for i in range(nx)] for j in range(ny)]
+                 for m in range(len(y))]
+        else:
+            k1 = f(y)
+            k2 = f(axpy(y, dt / 2, k1))
+            k3 = f(axpy(y, dt / 2, k2))
+            k4 = f(axpy(y, dt, k3))
+            y = [[[y[m][j][i] + dt / 6 * (k1[m][j][i] + 2 * k2[m][j][i] + 2 * k3[m][j][i] + k4[m][j][i])
+                   for i in range(nx)] for j in range(ny)] for m in range(len(y))]
+    return [np.array(a) for a in y]
+
+
+@pytest.mark.parametrize("model", ["diffusion", "barkley", "fk", "bocf", "fhn"])
+@pytest.mark.parametrize("stencil", ["lap5", "lap9"])
+@pytest.mark.parametrize("scheme", ["euler", "heun", "rk4"])
+@pytest.mark.parametrize("bc", ["noflux", "periodic"])
+def test_brute_force_scalar_loops_all_models(model, stencil, scheme, bc):
+    """The vectorised oracle agrees with scalar loops on a 5 x 4 grid, three
+    steps, to rounding (the loops sum in their own order)."""
+    base = {"diffusion": "fk_1024_rk4", "barkley": "barkley_1024_rk4_adjoint", "fk": "fk_1024_rk4",
+            "bocf": "bocf_2048_aniso_rk4", "fhn": "fhn_256_rk4"}[model]
+    w = ri.workload(base, model=model, stencil=stencil, scheme=scheme, nx=5, ny=4, bc=bc,
+                    D_perp=None, theta0=0.0, theta1=0.0)
+    p = oracle.Problem.from_workload(w, params=ri.params_array(model))
+    z = ri.random_fields(model, 5, 4, 11)
+    got = oracle.step(p, z, 3)
+    ref = _brute_step(p, z, 3)
+    for a, b in zip(got, ref):
+        assert np.max(np.abs(a - b)) <= 1e-13 * max(1.0, np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("model,name,n", [("fk", "fk_1024_rk4", 40), ("bocf", "bocf_2048_aniso_rk4", 36),
+                                          ("barkley", "barkley_1024_rk4_adjoint", 40)])
+def test_one_ulp_perturbation_floor_over_1000_steps(model, name, n):
+    """How far FP64 rounding differences can grow: two oracle runs of 1000
+    steps from initial states one ulp apart stay within 1e-12 (relative
+    L-infinity), below the 1e-11 parity gate, for the steep-front models."""
+    w = ri.workload(name, nx=n, ny=n)
+    p = oracle.Problem.from_workload(w, params=ri.params_array(model))
+    z0 = ri.initial_condition(w) if model != "bocf" else ri.bocf_ic(n, n, 3, amp=1e-2)
+    a = oracle.step(p, z0, 1000)
+    b = oracle.step(p, [np.nextafter(x, np.inf) for x in z0], 1000)
+    err = max(float(np.max(np.abs(x - y)) / np.max(np.abs(y))) for x, y in zip(a, b))
+    assert err <= 1e-12, err
+
+
+def test_fp64_floor_against_long_double():
+    """The same FitzHugh-Nagumo run (16 x 16, 9-point, RK4, 200 steps) in
+    FP64 and in extended precision differ by no more than the FP64
+    rounding floor."""
+    assert np.finfo(np.longdouble).eps < np.finfo(np.float64).eps
+    w = ri.workload("fhn_256_rk4", nx=16, ny=16)
+    p = oracle.Problem.from_workload(w, params=ri.params_array("fhn"))
+    z0 = ri.random_fields("fhn", 16, 16, 4)
+    a = oracle.step(p, z0, 200)
+    b = oracle.step(p, [x.astype(np.longdouble) for x in z0], 200)
+    assert b[0].dtype == np.longdouble
+    err = max(float(np.max(np.abs(x - y)) / np.max(np.abs(y))) for x, y in zip(a, b))
+    assert 0.0 < err <= 1e-13, err
