@@ -126,7 +126,9 @@ enum rd_status {
   RD_EINVAL = -1,       /* invalid argument (null pointer, bad size, ...)     */
   RD_EUNSUPPORTED = -2, /* valid but unsupported combination                  */
   RD_EWORKSPACE = -3,   /* workspace missing or smaller than required         */
-  RD_EHIP = -4          /* HIP runtime error (message holds the HIP string)   */
+  RD_EHIP = -4,         /* HIP runtime error (message holds the HIP string)   */
+  RD_ENONFINITE = -5    /* the result holds NaN or infinity (only while the
+                           check of rd_set_check_finite is enabled)           */
 };
 
 /* One integration problem (the problem statement of Sect. 3). */
@@ -287,6 +289,15 @@ int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows);
  * those timings finish; later calls reuse the choice.  Never inside a stream
  * capture.  Results do not depend on it. */
 int rd_set_autotune(int32_t enable);
+
+/* Enables (non-zero) or disables (0, the default) a debugging check: after
+ * rd_step, rd_jvp, rd_vjp and rd_step_batched have enqueued their work, a
+ * small kernel scans the fields they produced and the call returns
+ * RD_ENONFINITE if any value is NaN or infinite.  While enabled, every call
+ * synchronises its stream (so it cannot be captured in a HIP graph; calls
+ * inside a capture return RD_EUNSUPPORTED) and needs 256 more workspace bytes,
+ * which rd_workspace_bytes and rd_step_batched_workspace_bytes then include. */
+int rd_set_check_finite(int32_t enable);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* rd_last_error(void);

@@ -26,7 +26,8 @@ STENCILS_3D = ("lap7", "lap19", "lap27")
 OPS = {"step": 0, "jvp": 1, "vjp": 2, "batched": 3}
 N_FIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4, "fhn": 2}
 
-STATUS = {0: "RD_OK", -1: "RD_EINVAL", -2: "RD_EUNSUPPORTED", -3: "RD_EWORKSPACE", -4: "RD_EHIP"}
+STATUS = {0: "RD_OK", -1: "RD_EINVAL", -2: "RD_EUNSUPPORTED", -3: "RD_EWORKSPACE", -4: "RD_EHIP",
+          -5: "RD_ENONFINITE"}
 
 
 class RDError(RuntimeError):
@@ -74,6 +75,7 @@ def lib() -> C.CDLL:
             "rd_step_batched": ([P, C.c_int32, C.POINTER(_DPP), C.POINTER(_DPP), _PTR, C.c_size_t, _PTR], C.c_int),
             "rd_set_tile_rows": ([C.c_int32], C.c_int),
             "rd_set_autotune": ([C.c_int32], C.c_int),
+            "rd_set_check_finite": ([C.c_int32], C.c_int),
             "rd_get_tile_rows": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rd_set_kernel_variant": ([C.c_int32], C.c_int),
             "rd_get_plan": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
@@ -304,6 +306,14 @@ def vec_lincomb(y: torch.Tensor, beta: float, xs=(), coef=()) -> torch.Tensor:
 def set_autotune(enable: bool) -> None:
     """Enable or disable the band-height autotuner (see rd_set_autotune)."""
     _check(lib().rd_set_autotune(1 if enable else 0))
+
+
+def set_check_finite(enable: bool) -> None:
+    """Enable or disable the NaN/infinity check of every call's result (see
+    rd_set_check_finite); the cached workspaces are dropped because the
+    required sizes change."""
+    _check(lib().rd_set_check_finite(1 if enable else 0))
+    release_workspaces()
 
 
 def step(prob: Problem, fields, checkpoints: torch.Tensor | None = None):

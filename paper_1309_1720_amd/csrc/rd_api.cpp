@@ -415,17 +415,23 @@ int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out) {
   const size_t fb = field_bytes(p);
   if (is_3d(p->stencil)) {
     switch (op) {
-      case RD_OP_STEP: *out = workspace_3d(p, false); return RD_OK;
-      case RD_OP_JVP: *out = workspace_3d(p, true); return RD_OK;
-      case RD_OP_VJP: *out = workspace_vjp_3d(p); return RD_OK;
+      case RD_OP_STEP: *out = workspace_3d(p, false) + check_finite_bytes(); return RD_OK;
+      case RD_OP_JVP: *out = workspace_3d(p, true) + check_finite_bytes(); return RD_OK;
+      case RD_OP_VJP: *out = workspace_vjp_3d(p) + check_finite_bytes(); return RD_OK;
       case RD_OP_BATCHED: return fail(RD_EUNSUPPORTED, "batches of 3-D grids are not supported");
     }
     return fail(RD_EINVAL, "unknown op %d", op);
   }
   switch (op) {
-    case RD_OP_STEP: *out = nv * fb; return RD_OK;
-    case RD_OP_JVP: return workspace_jvp(p, out);
-    case RD_OP_VJP: return workspace_vjp(p, out);
+    case RD_OP_STEP: *out = nv * fb + check_finite_bytes(); return RD_OK;
+    case RD_OP_JVP:
+      workspace_jvp(p, out);
+      *out += check_finite_bytes();
+      return RD_OK;
+    case RD_OP_VJP:
+      workspace_vjp(p, out);
+      *out += check_finite_bytes();
+      return RD_OK;
     case RD_OP_BATCHED:
       return fail(RD_EINVAL, "use rd_step_batched_workspace_bytes for batched runs");
   }
@@ -445,16 +451,23 @@ int rd_step(const rd_problem* p, double* const* fields, double* checkpoints, voi
   rd_workspace_bytes(p, RD_OP_STEP, &need);
   rc = check_workspace(ws, ws_bytes, need);
   if (rc) return rc;
+  rc = check_finite_allowed((hipStream_t)hip_stream);
+  if (rc) return rc;
   const int nv = n_fields(p->model);
   hipStream_t s = (hipStream_t)hip_stream;
   KConst c;
   derive_constants(p, c);
-  if (is_3d(p->stencil))
-    return run_steps_3d(p, c, false, fields, (char*)ws, p->nsteps, checkpoints, p->checkpoint_every, s);
+  char* flag = (char*)ws + (need - check_finite_bytes());
+  const size_t cells = (size_t)p->nx * (size_t)p->ny * (size_t)(is_3d(p->stencil) ? p->nz : 1);
+  if (is_3d(p->stencil)) {
+    rc = run_steps_3d(p, c, false, fields, (char*)ws, p->nsteps, checkpoints, p->checkpoint_every, s);
+    return rc ? rc : check_finite(fields, nv, cells, flag, s, "rd_step");
+  }
   double* b[kMaxFields];
   for (int f = 0; f < nv; ++f) b[f] = (double*)((char*)ws + f * field_bytes(p));
   plan_geometry(p, c, false, fields, b, s);
-  return run_steps(p, c, false, fields, b, p->nsteps, checkpoints, p->checkpoint_every, s);
+  rc = run_steps(p, c, false, fields, b, p->nsteps, checkpoints, p->checkpoint_every, s);
+  return rc ? rc : check_finite(fields, nv, cells, flag, s, "rd_step");
 }
 
 int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents, void* ws,
@@ -471,9 +484,10 @@ int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents, 
       if (fields[i] == tangents[j]) return fail(RD_EINVAL, "fields[%d] aliases tangents[%d]", i, j);
   if (p->nsteps == 0) return RD_OK;
   size_t need = 0;
-  if (is_3d(p->stencil)) need = workspace_3d(p, true);
-  else workspace_jvp(p, &need);
+  rd_workspace_bytes(p, RD_OP_JVP, &need);
   rc = check_workspace(ws, ws_bytes, need);
+  if (rc) return rc;
+  rc = check_finite_allowed((hipStream_t)hip_stream);
   if (rc) return rc;
   double* a[kMaxPacked];
   double* b[kMaxPacked];
@@ -485,9 +499,15 @@ int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents, 
   hipStream_t s = (hipStream_t)hip_stream;
   KConst c;
   derive_constants(p, c);
-  if (is_3d(p->stencil)) return run_steps_3d(p, c, true, a, (char*)ws, p->nsteps, nullptr, 0, s);
-  plan_geometry(p, c, true, a, b, s);
-  return run_steps(p, c, true, a, b, p->nsteps, nullptr, 0, s);
+  char* flag = (char*)ws + (need - check_finite_bytes());
+  const size_t cells = (size_t)p->nx * (size_t)p->ny * (size_t)(is_3d(p->stencil) ? p->nz : 1);
+  if (is_3d(p->stencil)) {
+    rc = run_steps_3d(p, c, true, a, (char*)ws, p->nsteps, nullptr, 0, s);
+  } else {
+    plan_geometry(p, c, true, a, b, s);
+    rc = run_steps(p, c, true, a, b, p->nsteps, nullptr, 0, s);
+  }
+  return rc ? rc : check_finite(a, 2 * nv, cells, flag, s, "rd_jvp");
 }
 
 }  // extern "C"

@@ -51,7 +51,7 @@ static int batch_workspace(const rd_problem* probs, int32_t n, bool tangent, siz
     if (is_3d(probs[i].stencil)) return fail(RD_EUNSUPPORTED, "problem %d: batches of 3-D grids are not supported", i);
     total += (tangent ? 2 : 1) * (size_t)n_fields(probs[i].model) * field_bytes(&probs[i]);
   }
-  *out = total;
+  *out = total + check_finite_bytes();
   return RD_OK;
 }
 
@@ -90,6 +90,8 @@ extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* 
   if (!ws || ws_bytes < need)
     return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
   if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
+  rc = check_finite_allowed((hipStream_t)hip_stream);
+  if (rc) return rc;
 
   hipStream_t s = (hipStream_t)hip_stream;
   const int ns = n_stages(q.scheme);
@@ -191,6 +193,19 @@ extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* 
     e = launch_batch_kernel(tangent, q.model, q.stencil, q.scheme, args, s);
     if (e != hipSuccess) return hip_fail(e, "batched step launch");
     parity ^= 1;
+  }
+  if (check_finite_bytes()) {
+    char* flag = (char*)ws + (need - check_finite_bytes());
+    for (int32_t i = 0; i < nbatch; ++i) {
+      const size_t cells = (size_t)probs[i].nx * (size_t)probs[i].ny;
+      double* arrs[2 * kMaxFields];
+      for (int f = 0; f < nv; ++f) {
+        arrs[f] = fields[i][f];
+        if (tangent) arrs[nv + f] = tangents[i][f];
+      }
+      int rc2 = check_finite(arrs, tangent ? 2 * nv : nv, cells, flag, s, "rd_step_batched");
+      if (rc2) return fail(rc2, "problem %d: %s", i, rd_last_error());
+    }
   }
   return RD_OK;
 }

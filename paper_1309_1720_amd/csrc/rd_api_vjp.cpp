@@ -51,14 +51,21 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
   if (((uintptr_t)checkpoints) % 8 != 0) return fail(RD_EINVAL, "checkpoints is not 8-byte aligned");
   size_t need = 0;
   workspace_vjp(p, &need);
+  need += check_finite_bytes();
+  char* flag = (char*)ws + (need - check_finite_bytes());
   if (!ws || ws_bytes < need)
     return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
   if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
+  rc = check_finite_allowed((hipStream_t)hip_stream);
+  if (rc) return rc;
 
   if (is_3d(p->stencil)) {
     KConst c3;
     derive_constants(p, c3);
-    return vjp_3d(p, c3, checkpoints, cot, (char*)ws, (hipStream_t)hip_stream);
+    rc = vjp_3d(p, c3, checkpoints, cot, (char*)ws, (hipStream_t)hip_stream);
+    return rc ? rc
+              : check_finite(cot, n_fields(p->model), (size_t)p->nx * p->ny * p->nz, flag, (hipStream_t)hip_stream,
+                             "rd_vjp");
   }
   const int nv = n_fields(p->model);
   const int ns = n_stages(p->scheme);
@@ -162,5 +169,5 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
       std::swap(cur, oth);
     }
   }
-  return RD_OK;
+  return check_finite(cot, nv, cells, flag, s, "rd_vjp");
 }

@@ -51,6 +51,12 @@ int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hip
 
 int workspace_jvp(const rd_problem* p, size_t* out);
 
+// Optional finiteness check (rd_check.hip): extra workspace bytes while it is
+// enabled (0 otherwise), and the scan itself (RD_OK when disabled).
+size_t check_finite_bytes();
+int check_finite_allowed(hipStream_t s);  // RD_EUNSUPPORTED inside a capture while enabled
+int check_finite(double* const* f, int nf, size_t n, char* flag_ws, hipStream_t s, const char* what);
+
 // 3-D stencils (rd_api_3d.cpp).
 bool is_3d(int stencil);
 size_t workspace_3d(const rd_problem* p, bool tangent);

@@ -195,3 +195,22 @@ def test_3d_problems_validated_before_any_device_work():
             setattr(q, k, val)
         cq, _bq = q.to_c()
         assert B.lib().rd_vjp(C.byref(cq), C.c_void_p(1 << 20), fake, C.c_void_p(1 << 24), 1 << 30, None) in (-1, -2)
+
+
+def test_check_finite_knob_adds_workspace():
+    p = base_problem(nsteps=7, checkpoint_every=3)
+    base = {op: rd.workspace_bytes(p, op) for op in ("step", "jvp", "vjp")}
+    bb = C.c_size_t()
+    cp, _b = p.to_c()
+    assert B.lib().rd_step_batched_workspace_bytes(C.byref(cp), 1, 1, C.byref(bb)) == 0
+    rd.set_check_finite(True)
+    try:
+        for op, n in base.items():
+            assert rd.workspace_bytes(p, op) == n + 256, op
+        b2 = C.c_size_t()
+        assert B.lib().rd_step_batched_workspace_bytes(C.byref(cp), 1, 1, C.byref(b2)) == 0
+        assert b2.value == bb.value + 256
+    finally:
+        rd.set_check_finite(False)
+    assert rd.workspace_bytes(p, "step") == base["step"]
+    assert B.STATUS[-5] == "RD_ENONFINITE"
