@@ -102,7 +102,14 @@ def cpu_baseline(w, params, seconds: float):
         if el >= seconds or n >= 1000:
             break
     rate = w["nx"] * w["ny"] * n / el
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "host_cpu": cpu, "host_threads": os.cpu_count(),
             "sample": f"{n} RK4 steps of the {w['nx']}x{w['ny']} Fenton-Karma grid "
                       f"(NumPy, single thread), {el:.1f} s"}
 
@@ -227,6 +234,23 @@ def other_workloads(rd, torch, dev, only=None):
         out["fk_4096_rk4_beyond_llc"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
                                          "hbm_frac": 48 * cells * n / sec / HBM_PEAK,
                                          "plan": list(rd.get_plan(p, "step"))}
+        del z
+
+    if only in (None, "barkley_8192_rk4_beyond_llc"):
+        # HBM-bound 2-D probe beyond the 256 MB last-level cache: Barkley
+        # 8192^2 (1 GiB per state), 5-point, RK4, steps per launch tuned.
+        w = ri.workload("barkley_1024_rk4_adjoint", nx=8192, ny=8192, checkpoint_every=0)
+        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+        p = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=4)
+        rd.step(p, z)
+        n = 16
+        p.nsteps = n
+        sec = _timed(torch, stream, lambda: rd.step(p, z), reps=2)
+        cells = w["nx"] * w["ny"]
+        out["barkley_8192_rk4_beyond_llc"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
+                                              "steps_per_launch": rd.get_steps_per_launch(p),
+                                              "hbm_bytes_per_cell_update": 32,
+                                              "hbm_frac": 32 * cells * n / sec / HBM_PEAK}
         del z
 
     if only in (None, "fk_ensemble_64_jvp"):

@@ -19,6 +19,13 @@ The 3-D stage kernels (Fenton-Karma 256^3, 27-point, RK4) from three runs of
 FETCH_SIZE, WRITE_SIZE, each in OUT/stats, OUT/fetch, OUT/write):
 
        python bench_profile.py --stage3d OUT
+
+The HBM-bound 2-D probe (Barkley 8192^2, 5-point, RK4, two steps per
+launch) from the same three runs of `bench.py --only-workload
+barkley_8192_rk4_beyond_llc` (OUT/stats with the kernel trace, OUT/fetch,
+OUT/write):
+
+       python bench_profile.py --barkley8192 OUT
 """
 from __future__ import annotations
 
@@ -198,8 +205,52 @@ def main_3d(out: str) -> None:
     print("\n".join(lines))
 
 
+def main_barkley8192(out: str) -> None:
+    """Timed-phase launches only: the trace's last 16 dispatches of the
+    two-step sweep (the benchmark times two repetitions of 8 launches; the
+    earlier dispatches are warm-up and the tuner's trials)."""
+    kern = "rd::sweep_kernel<1, 5, 4, 0, 2, 0>"
+    cells = 8192 * 8192
+    cmd = lambda extra: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o bk -- "
+                         "python3 <repo>/bench.py --only-workload barkley_8192_rk4_beyond_llc")
+    trace = [r for r in _rows(os.path.join(out, "stats"), "*kernel_trace.csv") if kern in r["Kernel_Name"]]
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in trace][-16:]
+    avg = sum(durs) / len(durs)
+
+    def last(kind, counter):
+        rows = [r for r in _rows(os.path.join(out, kind), "*counter_collection.csv")
+                if kern in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        vals = [float(r["Counter_Value"]) for r in rows][-16:]
+        return sum(vals) / len(vals)
+    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.json")) as fh:
+        cal = json.load(fh)["calibration"]
+    rd_b = last("fetch", "FETCH_SIZE") * cal["fetch_scale"] * 1024
+    wr_b = last("write", "WRITE_SIZE") * cal["write_scale"] * 1024
+    state = 2 * 8 * cells
+    lines = ["# HBM-bound 2-D probe: Barkley 8192^2 (5-point, RK4, FP64), two steps per launch — kernel timings and traffic", "",
+             "Commands (each a run of its own), then `python3 <repo>/bench_profile.py --barkley8192 <out>`:", "",
+             "    " + cmd("--kernel-trace --stats"), "    " + cmd("--pmc FETCH_SIZE"), "    " + cmd("--pmc WRITE_SIZE"), "",
+             f"Kernel `{kern}`: the fused sweep chaining two RK4 steps per launch.  Timed-phase launches "
+             f"(the last 16 dispatches): average {avg:.1f} us (min {min(durs):.1f}, max {max(durs):.1f}).", "",
+             "| quantity | per launch (two steps) |", "|---|---|",
+             f"| state read + written once (algorithmic for the launch) | {2 * state / 1e9:.3f} GB |",
+             f"| single-step algorithmic bytes x 2 steps (32 B per cell-update) | {4 * state / 1e9:.3f} GB |",
+             f"| HBM read (FETCH_SIZE x {cal['fetch_scale']:.3f}) | {rd_b / 1e9:.3f} GB |",
+             f"| HBM written (WRITE_SIZE x {cal['write_scale']:.3f}) | {wr_b / 1e9:.3f} GB |", "",
+             f"Rate: {2 * cells / (avg * 1e-6):.3e} cell-updates/s; single-step algorithmic bandwidth "
+             f"{4 * state / (avg * 1e-6) / 1e12:.2f} TB/s ({4 * state / (avg * 1e-6) / 8e12 * 100:.0f}% of 8 TB/s); "
+             f"measured HBM traffic {(rd_b + wr_b) / (avg * 1e-6) / 1e12:.2f} TB/s "
+             f"({(rd_b + wr_b) / (2 * state):.2f}x the launch's algorithmic bytes: halo columns and band "
+             "ramps re-read).  Calibration factors from `profiles/fwd_fk_1024_rk4_counters.md`."]
+    with open(os.path.join(PROFILES, "fwd_barkley_8192_rk4_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "--stage3d":
+    if sys.argv[1] == "--barkley8192":
+        main_barkley8192(sys.argv[2])
+    elif sys.argv[1] == "--stage3d":
         main_3d(sys.argv[2])
     else:
         main(sys.argv[1], int(sys.argv[2]))
