@@ -186,10 +186,23 @@ def other_workloads(rd, torch, dev, only=None):
         rd.step(p, z)
         p.nsteps = w["nsteps"]
         sec = _timed(torch, stream, lambda: rd.step(p, z))
+        # the same 1000 steps captured once in a HIP graph and replayed (no
+        # per-launch host overhead)
+        gstream = torch.cuda.Stream(dev)
+        gstream.wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(gstream):
+            with torch.cuda.graph(graph, stream=gstream):
+                rd.step(p, z)
+        stream.wait_stream(gstream)
+        sec_g = _timed(torch, stream, graph.replay, reps=3)
         out["barkley_128_euler_1000"] = {"seconds": sec, "rate": 128 * 128 * w["nsteps"] / sec,
                                          "steps_per_launch": rd.get_steps_per_launch(p),
                                          "us_per_step": sec / w["nsteps"] * 1e6,
+                                         "us_per_step_graph_replay": sec_g / w["nsteps"] * 1e6,
+                                         "rate_graph_replay": 128 * 128 * w["nsteps"] / sec_g,
                                          "hbm_frac": 32 * 128 * 128 * w["nsteps"] / sec / HBM_PEAK}
+        del graph
 
     if only in (None, "fhn_256_rk4_1000"):
         # FitzHugh-Nagumo 256^2 (Eq. 3, u and v diffusive), 9-point, RK4, 1000 steps
