@@ -142,8 +142,10 @@ def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
     v = [torch.from_numpy(a).to(dev) for a in v_np]
     rd.jvp(p, z, v)
     jv = torch.cat([t.flatten() for t in v])
+    # v has unit norm over all 3 nx ny entries, so eps * v perturbs a cell by
+    # about eps / 1800: the range reaches the truncation side of the V-curve
     errs = {}
-    for k in range(9, 4, -1):
+    for k in range(9, -1, -1):
         eps = 10.0 ** (-k)
         zp = [torch.from_numpy(a + eps * b).to(dev) for a, b in zip(z0_np, v_np)]
         zm = [torch.from_numpy(a - eps * b).to(dev) for a, b in zip(z0_np, v_np)]
