@@ -164,16 +164,16 @@ void derive_constants(const rd_problem* p, KConst& c) {
       // tau_v+, tau_v1-, tau_v2-, tau_w+, tau_w-, tau_d, tau_0, tau_r, tau_si, k_si, u_csi, u_c, u_v
       FentonKarmaC& m = c.m.fk;
       m.inv_tau_vp = 1.0 / q[0];
-      m.tau_v1m = q[1];
       m.tau_v2m = q[2];
+      m.dtau_vm = q[1] - q[2];
       m.inv_tau_wp = 1.0 / q[3];
       m.inv_tau_wm = 1.0 / q[4];
       m.inv_tau_d = 1.0 / q[5];
       m.inv_tau_0 = 1.0 / q[6];
       m.inv_tau_r = 1.0 / q[7];
-      m.inv_2tau_si = 1.0 / (2.0 * q[8]);
-      m.k_si = q[9];
-      m.u_csi = q[10];
+      m.inv_tau_si = 1.0 / q[8];
+      m.lg_a = -2.0 * q[9];
+      m.lg_b = 2.0 * q[9] * q[10];
       m.u_c = q[11];
       m.u_v = q[12];
       break;
@@ -187,24 +187,24 @@ void derive_constants(const rd_problem* p, KConst& c) {
       m.th_vm = q[4];
       m.th_o = q[5];
       m.tau_v1m = q[6];
-      m.tau_v2m = q[7];
+      m.dtau_vm = q[7] - q[6];
       m.inv_tau_vp = 1.0 / q[8];
       m.tau_w1m = q[9];
       m.dtau_wm = q[10] - q[9];
-      m.k_wm = q[11];
-      m.u_wm = q[12];
+      m.lg_wm_a = -2.0 * q[11];
+      m.lg_wm_b = 2.0 * q[11] * q[12];
       m.inv_tau_wp = 1.0 / q[13];
       m.inv_tau_fi = 1.0 / q[14];
       m.tau_o1 = q[15];
       m.tau_o2 = q[16];
       m.tau_so1 = q[17];
       m.dtau_so = q[18] - q[17];
-      m.k_so = q[19];
-      m.u_so = q[20];
+      m.lg_so_a = -2.0 * q[19];
+      m.lg_so_b = 2.0 * q[19] * q[20];
       m.tau_s1 = q[21];
       m.tau_s2 = q[22];
-      m.k_s = q[23];
-      m.u_s = q[24];
+      m.lg_s_a = -2.0 * q[23];
+      m.lg_s_b = 2.0 * q[23] * q[24];
       m.inv_tau_si = 1.0 / q[25];
       m.inv_tau_winf = 1.0 / q[26];
       m.w_infstar = q[27];

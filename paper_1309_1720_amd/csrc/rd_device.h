@@ -24,14 +24,16 @@ constexpr double kAlphaDiag = 1.0 / 6.0;   // Eq. (6) diagonal weight
 // divisors are stored as reciprocals; u-dependent time constants are divided.
 struct BarkleyC { double b, inv_a, inv_eps; };
 struct FhnC { double eps, a1, a0; };
+// (1 + tanh(k (u - u_x))) / 2 is evaluated as 1 / (1 + e^(a u + b)) with
+// a = -2k, b = 2k u_x (lg_*); tau(u) blends as tau_1 + h (tau_2 - tau_1).
 struct FentonKarmaC {
-  double u_c, u_v, inv_tau_d, inv_tau_0, inv_tau_r, inv_2tau_si, k_si, u_csi,
-      tau_v1m, tau_v2m, inv_tau_vp, inv_tau_wm, inv_tau_wp;
+  double u_c, u_v, inv_tau_d, inv_tau_0, inv_tau_r, inv_tau_si, lg_a, lg_b,
+      tau_v2m, dtau_vm, inv_tau_vp, inv_tau_wm, inv_tau_wp;
 };
 struct BocfC {
-  double u_o, u_u, th_v, th_w, th_vm, th_o, tau_v1m, tau_v2m, inv_tau_vp, tau_w1m,
-      dtau_wm, k_wm, u_wm, inv_tau_wp, inv_tau_fi, tau_o1, tau_o2, tau_so1, dtau_so,
-      k_so, u_so, tau_s1, tau_s2, k_s, u_s, inv_tau_si, inv_tau_winf, w_infstar;
+  double u_o, u_u, th_v, th_w, th_vm, th_o, tau_v1m, dtau_vm, inv_tau_vp, tau_w1m,
+      dtau_wm, lg_wm_a, lg_wm_b, inv_tau_wp, inv_tau_fi, tau_o1, tau_o2, tau_so1, dtau_so,
+      lg_so_a, lg_so_b, tau_s1, tau_s2, lg_s_a, lg_s_b, inv_tau_si, inv_tau_winf, w_infstar;
 };
 union ModelC {
   BarkleyC bk;
@@ -229,10 +231,11 @@ __device__ __forceinline__ Dual step_h(Dual x, const KConst& c) {
 // (1 + tanh(x)) / 2 written as the logistic function 1 / (1 + exp(-2x)): the
 // same function, evaluated with one exp and one division (an FP64 tanh costs
 // several times more), and without the cancellation 1 + tanh(x) suffers for
-// x << 0.
+// x << 0.  The caller passes the exponent e = -2x, formed from u by one
+// multiply-add with host-computed constants.
 template <class T>
-__device__ __forceinline__ T half_one_plus_tanh(T x) {
-  return recip(1.0 + exp(-2.0 * x));
+__device__ __forceinline__ T logistic_of_exponent(T e) {
+  return recip(1.0 + exp(e));
 }
 
 // ---------------------------------------------------------------------------
@@ -288,8 +291,8 @@ template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
     const T one_p = 1.0 - p;
     const T j_fi = -(((v * p) * (1.0 - u)) * (u - m.u_c)) * m.inv_tau_d;
     const T j_so = mad(u * one_p, m.inv_tau_0, p * m.inv_tau_r);
-    const T j_si = -(w * (2.0 * half_one_plus_tanh(m.k_si * (u - m.u_csi)))) * m.inv_2tau_si;
-    const T tau_vm = mad(q, m.tau_v1m, (1.0 - q) * m.tau_v2m);
+    const T j_si = -(w * logistic_of_exponent(mad(u, m.lg_a, m.lg_b))) * m.inv_tau_si;
+    const T tau_vm = mad(q, m.dtau_vm, T(m.tau_v2m));
     f[0] = -((j_fi + j_so) + j_si);
     f[1] = mad(-(p * v), m.inv_tau_vp, (one_p * (1.0 - v)) * recip(tau_vm));
     f[2] = mad(one_p * (1.0 - w), m.inv_tau_wm, -(p * w) * m.inv_tau_wp);
@@ -303,7 +306,7 @@ template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
     const T p = step_h(u - m.u_c, c);
     const T q = step_h(u - m.u_v, c);
     const T one_p = 1.0 - p;
-    const T r_vm = recip(mad(q, m.tau_v1m, (1.0 - q) * m.tau_v2m));
+    const T r_vm = recip(mad(q, m.dtau_vm, T(m.tau_v2m)));
     al[1] = -(one_p * r_vm) - p * m.inv_tau_vp;
     be[1] = one_p * r_vm;
     al[2] = -(one_p * m.inv_tau_wm) - p * m.inv_tau_wp;
@@ -326,8 +329,8 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     const T h_w_neg = step_h(m.th_w - u, c);
     const T h_vm = step_h(u - m.th_vm, c);
     const T h_o = step_h(u - m.th_o, c);
-    const T r_vm = recip(mad(1.0 - h_vm, m.tau_v1m, h_vm * m.tau_v2m));
-    const T r_wm = recip(mad(m.dtau_wm, half_one_plus_tanh(m.k_wm * (u - m.u_wm)), T(m.tau_w1m)));
+    const T r_vm = recip(mad(h_vm, m.dtau_vm, T(m.tau_v1m)));
+    const T r_wm = recip(mad(m.dtau_wm, logistic_of_exponent(mad(u, m.lg_wm_a, m.lg_wm_b)), T(m.tau_w1m)));
     const T r_s = recip(mad(1.0 - h_w, m.tau_s1, h_w * m.tau_s2));
     const T v_inf = step_h(m.th_vm - u, c);
     const T w_inf = mad(1.0 - h_o, mad(-u, m.inv_tau_winf, 1.0), h_o * m.w_infstar);
@@ -336,7 +339,7 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     al[2] = mad(-h_w, m.inv_tau_wp, -(h_w_neg * r_wm));
     be[2] = (h_w_neg * w_inf) * r_wm;
     al[3] = -r_s;
-    be[3] = half_one_plus_tanh(m.k_s * (u - m.u_s)) * r_s;
+    be[3] = logistic_of_exponent(mad(u, m.lg_s_a, m.lg_s_b)) * r_s;
   }
 
   template <class T>
@@ -349,9 +352,9 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     const T h_w_neg = step_h(m.th_w - u, c);
     const T h_vm = step_h(u - m.th_vm, c);
     const T h_o = step_h(u - m.th_o, c);
-    const T r_vm = recip(mad(1.0 - h_vm, m.tau_v1m, h_vm * m.tau_v2m));           // 1/tau_v^-
-    const T r_wm = recip(mad(m.dtau_wm, half_one_plus_tanh(m.k_wm * (u - m.u_wm)), T(m.tau_w1m)));
-    const T r_so = recip(mad(m.dtau_so, half_one_plus_tanh(m.k_so * (u - m.u_so)), T(m.tau_so1)));
+    const T r_vm = recip(mad(h_vm, m.dtau_vm, T(m.tau_v1m)));           // 1/tau_v^-
+    const T r_wm = recip(mad(m.dtau_wm, logistic_of_exponent(mad(u, m.lg_wm_a, m.lg_wm_b)), T(m.tau_w1m)));
+    const T r_so = recip(mad(m.dtau_so, logistic_of_exponent(mad(u, m.lg_so_a, m.lg_so_b)), T(m.tau_so1)));
     const T r_s = recip(mad(1.0 - h_w, m.tau_s1, h_w * m.tau_s2));                 // 1/tau_s
     const T r_o = recip(mad(1.0 - h_o, m.tau_o1, h_o * m.tau_o2));                 // 1/tau_o
     const T v_inf = step_h(m.th_vm - u, c);
@@ -366,7 +369,7 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     const T alpha_w = mad(-h_w, m.inv_tau_wp, -(h_w_neg * r_wm));
     const T beta_w = (h_w_neg * w_inf) * r_wm;
     f[2] = mad(alpha_w, w, beta_w);
-    f[3] = (half_one_plus_tanh(m.k_s * (u - m.u_s)) - s) * r_s;
+    f[3] = (logistic_of_exponent(mad(u, m.lg_s_a, m.lg_s_b)) - s) * r_s;
   }
 };
 

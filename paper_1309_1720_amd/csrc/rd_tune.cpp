@@ -165,11 +165,14 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
       ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
       if (ok) per_step[i] = std::min(per_step[i], ms / (float)cands[i].k);
     }
+  // Near-ties (within 2%, about the run-to-run noise) go to the first
+  // candidate in list order, so that repeated tunings pick the same plan.
   float best_ms = 1e30f;
+  for (size_t i = 0; ok && i < cands.size(); ++i) best_ms = std::min(best_ms, per_step[i]);
   for (size_t i = 0; ok && i < cands.size(); ++i)
-    if (per_step[i] < best_ms) {
-      best_ms = per_step[i];
+    if (per_step[i] <= best_ms * 1.02f) {
       best = cands[i];
+      break;
     }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
