@@ -100,8 +100,13 @@ def test_dot_product_jvp_vjp(model, stencil, n, steps):
 
 @pytest.mark.slow
 def test_adjoint_workload_full_size_dot_and_fd():
-    """Barkley 1024^2, RK4, 4000 steps, checkpoints every 64: dot-product test
-    against the JVP and central differences in 4 seeded directions."""
+    """Barkley 1024^2, RK4, 4000 steps, checkpoints every 64: the exact check
+    is the dot-product test against the JVP (1e-12).  Central differences in
+    4 seeded directions are a loose cross-check: over this horizon the
+    rounding differences between the + and - runs are amplified, and the
+    measured error of the difference quotient against the gradient is no
+    better than 4e-5 at its best step (eps = 1e-5; 1.6e-4 at 1e-6, 5e-3 at
+    1e-4), so they are held to 1e-3."""
     w = ri.workload("barkley_1024_rk4_adjoint")
     _, pr = problems(w)
     z0 = ri.initial_condition(w)
@@ -111,12 +116,12 @@ def test_adjoint_workload_full_size_dot_and_fd():
     loss = lambda z: float(np.sum(z[0] ** 2) * w["dx"] ** 2)
     for k in range(4):
         v = ri.direction(2, 1024, 1024, 5000 + k)
-        eps = 1e-6
+        eps = 1e-5
         lp = loss(gpu_step(pr, [a + eps * b for a, b in zip(z0, v)]))
         lm = loss(gpu_step(pr, [a - eps * b for a, b in zip(z0, v)]))
         fd = (lp - lm) / (2 * eps)
         ad = dot(g, v)
-        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-12), (k, fd, ad)
+        assert abs(fd - ad) <= 1e-3 * max(abs(ad), 1e-12), (k, fd, ad)
     v = ri.direction(2, 1024, 1024, 5100)
     zt, vt = dev(z0), dev(v)
     rd.jvp(pr, zt, vt)
