@@ -33,6 +33,9 @@ last stage down to the first, Ybar_s = J(Y_s)^T kbar_s, zbar += Ybar_s and
 kbar_j += A_sj Ybar_s (j < s).  J(Y)^T a = (L^T a_u + sum_m dN_m/du a_m,
 sum_m dN_m/dh a_m), with L^T the transposed sparse operator and the
 pointwise Jacobian from complex-step differentiation of the reaction.
+A gate step is transposed as its pointwise part (complex-step columns of the
+voltage's reaction update and of each gate update) plus dt L^T on the
+diffusive field.
 """
 from __future__ import annotations
 
@@ -102,6 +105,48 @@ def _gate_step(prob: Problem, z):
                 out.append((zf + dt * b) / (1.0 - dt * a))
         else:
             out.append(zf + dt * k[f])
+    return out
+
+
+def _gate_pointwise(prob: Problem, z):
+    """The pointwise part of one gate step: the non-gate fields' explicit
+    Euler step on the reaction alone (the diffusion term is linear and is
+    transposed separately) and each gate's Rush-Larsen or implicit-Euler
+    update, exactly as `_gate_step` forms them."""
+    dt = prob.dt
+    n = reaction(prob, z)
+    coef = gate_coefficients(prob, z)
+    out = []
+    for f, zf in enumerate(z):
+        if f in coef:
+            a, b = coef[f]
+            if prob.scheme == "rush_larsen":
+                x = a * dt
+                out.append(zf * np.exp(x) + (b / a) * _expm1(x))
+            else:
+                out.append((zf + dt * b) / (1.0 - dt * a))
+        else:
+            out.append(zf + dt * n[f])
+    return out
+
+
+def _gate_step_adjoint(prob: Problem, z, lam, Lt):
+    """lam_n for one gate step: the transposed pointwise Jacobian of
+    `_gate_pointwise` (complex-step columns) applied to lam, plus
+    dt L^T lam on the diffusive fields."""
+    nv = len(z)
+    base = [np.asarray(a, dtype=np.complex128) for a in z]
+    out = []
+    for l in range(nv):
+        pert = list(base)
+        pert[l] = base[l] + 1j * COMPLEX_STEP
+        col = _gate_pointwise(prob, pert)
+        acc = (np.imag(col[0]) / COMPLEX_STEP) * lam[0]
+        for m in range(1, nv):
+            acc = acc + (np.imag(col[m]) / COMPLEX_STEP) * lam[m]
+        out.append(acc)
+    for f, lt in Lt.items():
+        out[f] = out[f] + (lt @ (prob.dt * lam[f]).ravel()).reshape(lam[f].shape)
     return out
 
 
@@ -191,6 +236,8 @@ def step_adjoint(prob: Problem, z, lam, Lt=None):
     `transposed_operators`."""
     if Lt is None:
         Lt = transposed_operators(prob)
+    if prob.scheme in ("rush_larsen", "implicit_euler"):
+        return _gate_step_adjoint(prob, z, lam, Lt)
     A, B = _coefficients(prob)
     ys = stage_states(prob, z)
     S = len(B)

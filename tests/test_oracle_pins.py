@@ -799,3 +799,35 @@ def test_fp64_floor_against_long_double():
     assert b[0].dtype == np.longdouble
     err = max(float(np.max(np.abs(x - y)) / np.max(np.abs(y))) for x, y in zip(a, b))
     assert 0.0 < err <= 1e-13, err
+
+
+@pytest.mark.parametrize("model", ["fk", "bocf"])
+@pytest.mark.parametrize("stencil", ["lap5", "lap9", "lap9_aniso"])
+@pytest.mark.parametrize("scheme", ["rush_larsen", "implicit_euler"])
+def test_gate_scheme_adjoint_dot_product(model, stencil, scheme):
+    """The gate steps' adjoint against the complex-step tangent of the whole
+    flow (an independent derivative): <J v, w> = <v, J^T w>."""
+    p, z0 = case_problem(model, stencil, scheme)
+    nv = len(z0)
+    v = ri.direction(nv, p.nx, p.ny, 31)
+    w = ri.direction(nv, p.nx, p.ny, 32)
+    _, jv = oracle.jvp(p, z0, v, 9)
+    jtw = oracle.vjp(p, z0, w, 9, checkpoint_every=4)
+    a = float(flat(jv) @ flat(w))
+    b = float(flat(v) @ flat(jtw))
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+@pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap9", "rush_larsen"), ("bocf", "lap5", "implicit_euler")])
+def test_gate_scheme_vjp_equals_transpose_of_dense_jacobian(model, stencil, scheme):
+    p, z0 = case_problem(model, stencil, scheme, nx=4, ny=3)
+    nv, n = len(z0), 12
+    J = np.zeros((nv * n, nv * n))
+    for k in range(nv * n):
+        e = np.zeros(nv * n)
+        e[k] = 1.0
+        _, jv = oracle.jvp(p, z0, [a.reshape(3, 4) for a in np.split(e, nv)], 3)
+        J[:, k] = flat(jv)
+    lam = ri.direction(nv, 4, 3, 5)
+    got = flat(oracle.vjp(p, z0, lam, 3, checkpoint_every=2))
+    assert np.max(np.abs(got - J.T @ flat(lam))) <= 1e-13 * np.max(np.abs(J.T @ flat(lam)))
