@@ -13,6 +13,9 @@
 // symmetric; its transpose is applied in gather form (flux_transpose).  J_N(Y)^T comes from the
 // reaction's Jacobian columns, evaluated on dual numbers.
 //
+// The gate schemes (one stage) transpose as lambda_n = J_P(z)^T lambda +
+// dt L^T lambda_u, with P the step's pointwise part (gate_point_jt).
+//
 // The stage inputs Y_2 .. Y_S are produced beforehand by the stage-input mode
 // of the sweep kernel (Y_1 = z_n).  This kernel uses the same decomposition
 // as the sweep: one wavefront per 64-column strip and row band, halo NS, and
@@ -45,6 +48,30 @@ __device__ __forceinline__ void reaction_jt(const KConst& c, const double* y, co
     double acc = kd[0].d * a[0];
 #pragma unroll
     for (int m = 1; m < NV; ++m) acc = acc + kd[m].d * a[m];
+    out[l] = acc;
+  }
+}
+
+// out = J_P(y)^T lam for the pointwise part P of a gate step (GATE 1:
+// Rush-Larsen, 2: implicit Euler; gated models): the voltage's explicit
+// Euler step on the reaction alone and each gate's update, differentiated
+// column by column on dual numbers.  The diffusion term of the voltage is
+// linear; its transpose (dt L^T lam_u) is added by the caller.
+template <int MODEL, int GATE>
+__device__ __forceinline__ void gate_point_jt(const KConst& c, const double* y, const double* lam,
+                                              double* out) {
+  constexpr int NV = ModelTraits<MODEL>::NV;
+  static_assert(ModelTraits<MODEL>::GATED && ModelTraits<MODEL>::NDIFF == 1, "gated models only");
+#pragma unroll
+  for (int l = 0; l < NV; ++l) {
+    Dual yd[NV], kd[NV], al[NV], be[NV];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) yd[f] = Dual(y[f], f == l ? 1.0 : 0.0);
+    Reaction<MODEL>::template rates<Dual>(c, yd, kd);
+    Reaction<MODEL>::template gates<Dual>(c, yd, al, be);
+    double acc = (yd[0] + c.dt * kd[0]).d * lam[0];
+#pragma unroll
+    for (int g = 1; g < NV; ++g) acc = acc + gate_step<GATE>(yd[g], al[g], be[g], c.dt).d * lam[g];
     out[l] = acc;
   }
 }
@@ -139,9 +166,10 @@ template <> struct AdjCoef<4> {
 // four dual-number Jacobian columns would spill otherwise).
 template <int MODEL> struct AdjOccupancy { static constexpr int value = MODEL == RD_MODEL_BOCF ? 1 : 2; };
 
-template <int MODEL, int STENCIL, int NS>
+template <int MODEL, int STENCIL, int NS, int GATE = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjOccupancy<MODEL>::value)))
 void adjoint_kernel(AdjArgs a) {
+  static_assert(GATE == 0 || NS == 1, "gate schemes have one stage");
   constexpr int NV = ModelTraits<MODEL>::NV;
   constexpr int NDF = ModelTraits<MODEL>::NDIFF;  // diffusive fields 0 .. NDF-1
   constexpr int TX = kWave - 2 * NS;
@@ -280,11 +308,21 @@ void adjoint_kernel(AdjArgs a) {
         for (int f = 0; f < NV; ++f) y[f] = a.ys[j - 2][f][o];
       }
       double yb[NV];
-      reaction_jt<MODEL>(c, y, kb, yb);
+      if constexpr (GATE != 0) {
+        // lambda_n = J_P^T lambda + L^T (dt lambda_u): the whole new value
+        gate_point_jt<MODEL, GATE>(c, y, lr[lag], yb);
 #pragma unroll
-      for (int d = 0; d < NDF; ++d) yb[d] = yb[d] + lapT[d];
+        for (int d = 0; d < NDF; ++d) yb[d] = yb[d] + lapT[d];
+#pragma unroll
+        for (int f = 0; f < NV; ++f) lacc[lag - 1][f] = yb[f];
+      } else {
+        reaction_jt<MODEL>(c, y, kb, yb);
+#pragma unroll
+        for (int d = 0; d < NDF; ++d) yb[d] = yb[d] + lapT[d];
+      }
 
-      if (j == NS) {
+      if (GATE != 0) {
+      } else if (j == NS) {
 #pragma unroll
         for (int f = 0; f < NV; ++f) lacc[lag - 1][f] = lr[lag][f] + yb[f];
       } else {
@@ -307,12 +345,22 @@ void adjoint_kernel(AdjArgs a) {
   }
 }
 
-template <int MODEL, int STENCIL, int NS>
+template <int MODEL, int STENCIL, int NS, int GATE = 0>
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t stream) {
   const int waves = a.c.nsx * a.c.nby;
   const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((adjoint_kernel<MODEL, STENCIL, NS>), dim3(blocks), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL((adjoint_kernel<MODEL, STENCIL, NS, GATE>), dim3(blocks), dim3(256), 0, stream, a);
   return hipGetLastError();
+}
+
+// The gate schemes' adjoint (one stage; gated models only).
+template <int MODEL, int STENCIL>
+hipError_t launch_adjoint_gate(int scheme, const AdjArgs& a, hipStream_t s) {
+  if constexpr (ModelTraits<MODEL>::GATED) {
+    if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_adjoint<MODEL, STENCIL, 1, 1>(a, s);
+    if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_adjoint<MODEL, STENCIL, 1, 2>(a, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int MODEL>
@@ -322,17 +370,17 @@ hipError_t launch_adjoint_model(int stencil, int scheme, const AdjArgs& a, hipSt
       if (scheme == RD_SCHEME_EULER) return launch_adjoint<MODEL, RD_LAP5, 1>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_adjoint<MODEL, RD_LAP5, 2>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_adjoint<MODEL, RD_LAP5, 4>(a, s);
-      break;
+      return launch_adjoint_gate<MODEL, RD_LAP5>(scheme, a, s);
     case RD_LAP9:
       if (scheme == RD_SCHEME_EULER) return launch_adjoint<MODEL, RD_LAP9, 1>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_adjoint<MODEL, RD_LAP9, 2>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_adjoint<MODEL, RD_LAP9, 4>(a, s);
-      break;
+      return launch_adjoint_gate<MODEL, RD_LAP9>(scheme, a, s);
     case RD_LAP9_ANISO:
       if (scheme == RD_SCHEME_EULER) return launch_adjoint<MODEL, RD_LAP9_ANISO, 1>(a, s);
       if (scheme == RD_SCHEME_HEUN) return launch_adjoint<MODEL, RD_LAP9_ANISO, 2>(a, s);
       if (scheme == RD_SCHEME_RK4) return launch_adjoint<MODEL, RD_LAP9_ANISO, 4>(a, s);
-      break;
+      return launch_adjoint_gate<MODEL, RD_LAP9_ANISO>(scheme, a, s);
   }
   return hipErrorInvalidValue;
 }
