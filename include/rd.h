@@ -76,8 +76,8 @@ enum rd_model {
  * alpha g + beta with alpha, beta frozen at z_n, takes
  *   Rush-Larsen:     g' = g e^{alpha dt} + (beta/alpha)(e^{alpha dt} - 1)
  *   implicit Euler:  g' = (g + dt beta) / (1 - dt alpha).
- * rd_step, rd_jvp and rd_step_batched support them, and rd_vjp on the 2-D
- * stencils; other models return RD_EUNSUPPORTED. */
+ * rd_step, rd_jvp, rd_vjp and rd_step_batched support them; other models
+ * return RD_EUNSUPPORTED. */
 enum rd_scheme {
   RD_SCHEME_EULER = 1,
   RD_SCHEME_HEUN = 2,
@@ -104,7 +104,7 @@ enum rd_scheme {
  * Both isotropic members reduce to Eq. (6) on a single plane with mirrored
  * z-neighbours, as RD_LAP7 reduces to RD_LAP5.  Boundaries as in 2-D, in all
  * three directions.  rd_step and rd_jvp take them (every model and scheme),
- * rd_vjp too (every model; Euler, Heun, RK4); rd_step_batched returns
+ * rd_vjp too (every model and scheme); rd_step_batched returns
  * RD_EUNSUPPORTED. */
 enum rd_stencil {
   RD_LAP5 = 5, RD_LAP9 = 9, RD_LAP9_ANISO = 10,
@@ -211,8 +211,8 @@ int rd_jvp(const rd_problem* p, double* const* fields, double* const* tangents,
  * States between checkpoints are recomputed into the workspace.
  * All stencils: the anisotropic flux form, which is not symmetric, is
  * transposed face by face (zero boundary flux and mirrored ghosts included).
- * The gate schemes (2-D stencils) transpose as the pointwise Jacobian of the
- * step's reaction and gate updates plus dt L^T on the voltage.
+ * The gate schemes transpose as the pointwise Jacobian of the step's
+ * reaction and gate updates plus dt L^T on the voltage.
  */
 int rd_vjp(const rd_problem* p, const double* checkpoints, double* const* cotangents,
            void* ws, size_t ws_bytes, void* hip_stream);

@@ -6,7 +6,8 @@
 //   kbar_j = B_j lambda + a_{j+1} Ybar_{j+1}      (no second term for j = S)
 //   Ybar_j = J_N(Y_j)^T kbar_j + L kbar_j          (L on the diffusive fields)
 //   zbar  += Ybar_j,
-// and lambda_n = zbar after j = 1.  The 3-D operators are symmetric under
+// and lambda_n = zbar after j = 1 (a gate step: lambda_n = J_P(z)^T lambda +
+// dt L lambda_u, P its pointwise part).  The 3-D operators are symmetric under
 // both boundary rules (mirrored ghosts, periodic wrap), so L^T = L.  Y_j is a
 // pointwise input (the reaction's Jacobian); the operator acts on kbar_j,
 // which is formed at the neighbour rows from lambda and Ybar_{j+1} while the
@@ -35,8 +36,9 @@ struct Adj3Args {
   double* yb_out[kMaxFields];         // Ybar_j (WRITEYB)
 };
 
-template <int MODEL, int STENCIL, bool HASKP, bool HASYB, bool WRITEYB>
+template <int MODEL, int STENCIL, bool HASKP, bool HASYB, bool WRITEYB, int GATE = 0>
 __global__ __launch_bounds__(kStage3Waves* kWave) void adjoint3d_kernel(Adj3Args a) {
+  static_assert(GATE == 0 || (!HASKP && !HASYB && !WRITEYB), "gate schemes have one stage");
   constexpr int NV = ModelTraits<MODEL>::NV;
   constexpr int ND = ModelTraits<MODEL>::NDIFF;
   constexpr bool DIAG = STENCIL != RD_LAP7;
@@ -108,7 +110,15 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void adjoint3d_kernel(Adj3Args
       else y[f] = a.z[f][o];
       kb[f] = kbar(f, o);
     }
-    reaction_jt<MODEL>(c, y, kb, yb);
+    if constexpr (GATE != 0) {
+      // gate step: lambda_n = J_P(z)^T lambda + L (dt lambda_u), the whole new value
+      double lam_c[NV];
+#pragma unroll
+      for (int f = 0; f < NV; ++f) lam_c[f] = a.lam[f][o];
+      gate_point_jt<MODEL, GATE>(c, y, lam_c, yb);
+    } else {
+      reaction_jt<MODEL>(c, y, kb, yb);
+    }
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       const double cen = U[1][d];
@@ -127,8 +137,8 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void adjoint3d_kernel(Adj3Args
     if (out_col) {
 #pragma unroll
       for (int f = 0; f < NV; ++f) {
-        const double zs = a.zs_in[f][o];
-        __builtin_nontemporal_store(zs + yb[f], &a.zs_out[f][o]);
+        const double zs = GATE != 0 ? 0.0 : a.zs_in[f][o];
+        __builtin_nontemporal_store(GATE != 0 ? yb[f] : zs + yb[f], &a.zs_out[f][o]);
         if constexpr (WRITEYB) __builtin_nontemporal_store(yb[f], &a.yb_out[f][o]);
       }
     }
@@ -149,7 +159,7 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void adjoint3d_kernel(Adj3Args
 // Reverse-stage kinds: the last stage (no Ybar_{j+1}), middle stages, the
 // first stage of a multi-stage scheme (no k_0, no Ybar output), and Euler's
 // only stage.
-enum Adj3Kind { kA3Last = 0, kA3Mid = 1, kA3First = 2, kA3Only = 3 };
+enum Adj3Kind { kA3Last = 0, kA3Mid = 1, kA3First = 2, kA3Only = 3, kA3GateRL = 4, kA3GateIE = 5 };
 
 template <int MODEL, int STENCIL>
 hipError_t launch_adjoint3d_st(int kind, const Adj3Args& a, hipStream_t s) {
@@ -159,6 +169,16 @@ hipError_t launch_adjoint3d_st(int kind, const Adj3Args& a, hipStream_t s) {
     case kA3Mid: hipLaunchKernelGGL((adjoint3d_kernel<MODEL, STENCIL, true, true, true>), grid, block, 0, s, a); break;
     case kA3First: hipLaunchKernelGGL((adjoint3d_kernel<MODEL, STENCIL, false, true, false>), grid, block, 0, s, a); break;
     case kA3Only: hipLaunchKernelGGL((adjoint3d_kernel<MODEL, STENCIL, false, false, false>), grid, block, 0, s, a); break;
+    case kA3GateRL:
+    case kA3GateIE:
+      if constexpr (ModelTraits<MODEL>::GATED) {
+        if (kind == kA3GateRL)
+          hipLaunchKernelGGL((adjoint3d_kernel<MODEL, STENCIL, false, false, false, 1>), grid, block, 0, s, a);
+        else
+          hipLaunchKernelGGL((adjoint3d_kernel<MODEL, STENCIL, false, false, false, 2>), grid, block, 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

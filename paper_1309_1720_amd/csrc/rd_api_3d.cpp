@@ -242,7 +242,9 @@ int vjp_3d(const rd_problem* p, const KConst& c, const double* checkpoints, doub
         g.a_in = stage_a(c, ns, j);
         g.b_j = stage_b(c, ns, j);
         g.a_next = j < ns - 1 ? stage_a(c, ns, j + 1) : 0.0;
-        const int kind = ns == 1 ? kA3Only : (j == ns - 1 ? kA3Last : (j == 0 ? kA3First : kA3Mid));
+        const int kind = gate_scheme(p->scheme)
+                             ? (p->scheme == RD_SCHEME_RUSH_LARSEN ? kA3GateRL : kA3GateIE)
+                             : ns == 1 ? kA3Only : (j == ns - 1 ? kA3Last : (j == 0 ? kA3First : kA3Mid));
         hipError_t e = launch_adjoint3d(p->model, p->stencil, kind, g, s);
         if (e != hipSuccess) return hip_fail(e, "3-D adjoint stage launch");
       }

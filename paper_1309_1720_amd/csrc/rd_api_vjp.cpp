@@ -43,8 +43,6 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
   if (rc) return rc;
   rc = validate_fields(p, cot, "cotangents");
   if (rc) return rc;
-  if (gate_scheme(p->scheme) && is_3d(p->stencil))
-    return fail(RD_EUNSUPPORTED, "rd_vjp of the gate schemes supports the 2-D stencils");
   if (p->checkpoint_every <= 0) return fail(RD_EINVAL, "rd_vjp needs checkpoint_every > 0");
   if (p->nsteps == 0) return RD_OK;
   if (!checkpoints) return fail(RD_EINVAL, "checkpoints is NULL");

@@ -151,20 +151,20 @@ def test_krylov_vector_calls_validate_before_launch():
     assert L.rd_vec_lincomb(0x7001, 1.0, xs, coef, 3, 10, None) == -1
 
 
-def test_gate_schemes_need_gated_models_and_2d_for_the_adjoint():
+def test_gate_schemes_need_gated_models():
     w = ri.workload("barkley_128_euler", scheme="rush_larsen")
     pb = rd.Problem.from_workload(w, ri.params_array("barkley"))
     cp, _b = pb.to_c()
     out = C.c_size_t(0)
     assert B.lib().rd_workspace_bytes(C.byref(cp), 0, C.byref(out)) == -2
     assert "gated model" in B.lib().rd_last_error().decode()
-    # the gate schemes' adjoint exists for the 2-D stencils; 3-D is refused
-    # before anything is enqueued
-    pf = base_problem(scheme="implicit_euler", checkpoint_every=2, stencil="lap19", nz=3)
-    cpf, _bf = pf.to_c()
-    fake = (C.c_void_p * 3)(0x10000, 0x20000, 0x30000)
-    rc = B.lib().rd_vjp(C.byref(cpf), 0x40000, fake, 0x100000, 1 << 30, None)
-    assert rc == -2 and "2-D stencils" in B.lib().rd_last_error().decode()
+    # rd_vjp refuses a gate scheme on a model without gates before anything
+    # is enqueued
+    pb.checkpoint_every = 2
+    cpb, _b2 = pb.to_c()
+    fake = (C.c_void_p * 2)(0x10000, 0x20000)
+    rc = B.lib().rd_vjp(C.byref(cpb), 0x40000, fake, 0x100000, 1 << 30, None)
+    assert rc == -2 and "gated model" in B.lib().rd_last_error().decode()
 
 
 def test_3d_problems_validated_before_any_device_work():
@@ -189,9 +189,9 @@ def test_3d_problems_validated_before_any_device_work():
     v, r = C.c_int32(), C.c_int32()
     assert B.lib().rd_get_plan(C.byref(cp), 0, C.byref(v), C.byref(r)) == -2
     assert B.lib().rd_step_batched_workspace_bytes(C.byref(cp), 1, 0, C.byref(C.c_size_t())) == -2
-    # rejected before any launch: no checkpoint spacing, a gate scheme
+    # rejected before any launch: no checkpoint spacing, no planes
     fake = (C.c_void_p * 3)(1 << 16, 2 << 16, 3 << 16)
-    for kw in ({"checkpoint_every": 0}, {"scheme": "rush_larsen"}):
+    for kw in ({"checkpoint_every": 0}, {"nz": 0}):
         q = base_problem(stencil="lap27", nx=30, ny=20, nz=10, checkpoint_every=5)
         for k, val in kw.items():
             setattr(q, k, val)

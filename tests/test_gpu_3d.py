@@ -226,6 +226,19 @@ def test_3d_vjp_matches_oracle(model, stencil, scheme):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("model,stencil,scheme,bc", [("fk", "lap27", "rush_larsen", "noflux"),
+                                                     ("bocf", "lap19", "implicit_euler", "periodic"),
+                                                     ("fk", "lap7", "implicit_euler", "noflux"),
+                                                     ("bocf", "lap27", "rush_larsen", "noflux")])
+def test_3d_vjp_gate_schemes_match_oracle(model, stencil, scheme, bc):
+    po, pr, z0 = setup(model, stencil, scheme, 20, 9, 6, 5, bc=bc, checkpoint_every=2)
+    lam = ri.direction(len(z0), 20, 9, 23, nz=6)
+    ref = oracle.vjp(po, z0, lam, 5, checkpoint_every=2)
+    err = rel_linf(gpu_vjp(pr, z0, lam), ref)
+    print(f"3-D {model} {stencil} {scheme} {bc}: adjoint rel-Linf {err:.3e}")
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("model,stencil,bc", [("fk", "lap27", "periodic"), ("fhn", "lap19", "noflux"),
                                               ("bocf", "lap7", "periodic")])
 def test_3d_vjp_periodic_and_degenerate(model, stencil, bc):
