@@ -104,8 +104,8 @@ enum rd_scheme {
  * Both isotropic members reduce to Eq. (6) on a single plane with mirrored
  * z-neighbours, as RD_LAP7 reduces to RD_LAP5.  Boundaries as in 2-D, in all
  * three directions.  rd_step and rd_jvp take them (every model and scheme),
- * rd_vjp too (every model and scheme); rd_step_batched returns
- * RD_EUNSUPPORTED. */
+ * rd_vjp too (every model and scheme), and rd_step_batched (each 3-D
+ * instance's stage launches in turn). */
 enum rd_stencil {
   RD_LAP5 = 5, RD_LAP9 = 9, RD_LAP9_ANISO = 10,
   RD_LAP7 = 7, RD_LAP19 = 19, RD_LAP27 = 27
@@ -218,9 +218,11 @@ int rd_vjp(const rd_problem* p, const double* checkpoints, double* const* cotang
            void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
- * rd_step_batched -- advance `nbatch` independent problems (same model,
- * scheme and stencil; grids, dx, dt, D and parameters may differ; all with
- * the same nsteps) in one launch per step (an addition to the paper).
+ * rd_step_batched -- advance `nbatch` independent problems that differ only
+ * in their grid sizes (model, scheme, stencil, boundary rule, dx, dt, nsteps,
+ * diffusivities, fibre angles and parameters agree; RD_EUNSUPPORTED
+ * otherwise) in one launch per step over all of them (an addition to the
+ * paper); 3-D instances run their stage launches one instance after another.
  *   fields[b]    host array of n_fields device pointers of problem b.
  *   tangents     NULL for a forward-only run, else tangents[b] as in
  *                rd_jvp: the tangents are advanced with the states.

@@ -24,7 +24,6 @@ static hipError_t launch_batch_kernel(bool tangent, int model, int stencil, int 
 // Everything except the grid size must agree across the batch.
 static int check_uniform(const rd_problem* probs, int32_t n) {
   const rd_problem& q = probs[0];
-  if (is_3d(q.stencil)) return fail(RD_EUNSUPPORTED, "batches of 3-D grids are not supported");
   for (int32_t i = 1; i < n; ++i) {
     const rd_problem& p = probs[i];
     const bool aniso = q.stencil == RD_LAP9_ANISO;
@@ -41,15 +40,19 @@ static int check_uniform(const rd_problem* probs, int32_t n) {
 
 static size_t table_bytes(int32_t n) { return align_up(sizeof(BatchInst) * (size_t)n, 256); }
 
+// 2-D: the descriptor table and one partner array per instance array.  3-D:
+// each instance's own stage workspace (its grids run one after another).
 static int batch_workspace(const rd_problem* probs, int32_t n, bool tangent, size_t* out) {
   if (!probs) return fail(RD_EINVAL, "problems is NULL");
   if (n < 1 || n > 65536) return fail(RD_EINVAL, "nbatch %d outside [1, 65536]", n);
-  size_t total = table_bytes(n);
+  size_t total = is_3d(probs[0].stencil) ? 0 : table_bytes(n);
   for (int32_t i = 0; i < n; ++i) {
     int rc = validate(&probs[i]);
     if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
-    if (is_3d(probs[i].stencil)) return fail(RD_EUNSUPPORTED, "problem %d: batches of 3-D grids are not supported", i);
-    total += (tangent ? 2 : 1) * (size_t)n_fields(probs[i].model) * field_bytes(&probs[i]);
+    if (is_3d(probs[i].stencil))
+      total += workspace_3d(&probs[i], tangent);
+    else
+      total += (tangent ? 2 : 1) * (size_t)n_fields(probs[i].model) * field_bytes(&probs[i]);
   }
   *out = total + check_finite_bytes();
   return RD_OK;
@@ -65,35 +68,14 @@ extern "C" int rd_step_batched_workspace_bytes(const rd_problem* probs, int32_t 
   return batch_workspace(probs, nbatch, with_tangents != 0, out);
 }
 
-extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* const* fields,
-                               double* const* const* tangents, void* ws, size_t ws_bytes,
-                               void* hip_stream) {
+// The 2-D batch: one descriptor table and one launch per step over all
+// instances (see the kernel in rd_batch.h).
+static int run_batched_2d(const rd_problem* probs, int32_t nbatch, double* const* const* fields,
+                          double* const* const* tangents, void* ws, hipStream_t s) {
   const bool tangent = tangents != nullptr;
-  size_t need = 0;
-  int rc = batch_workspace(probs, nbatch, tangent, &need);
-  if (rc) return rc;
-  rc = check_uniform(probs, nbatch);
-  if (rc) return rc;
-  if (!fields) return fail(RD_EINVAL, "fields is NULL");
   const rd_problem& q = probs[0];
   const int nv = n_fields(q.model);
   const int nf = (tangent ? 2 : 1) * nv;
-  for (int32_t i = 0; i < nbatch; ++i) {
-    rc = validate_fields(&probs[i], fields[i], "fields");
-    if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
-    if (tangent) {
-      rc = validate_fields(&probs[i], tangents[i], "tangents");
-      if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
-    }
-  }
-  if (q.nsteps == 0) return RD_OK;
-  if (!ws || ws_bytes < need)
-    return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
-  if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
-  rc = check_finite_allowed((hipStream_t)hip_stream);
-  if (rc) return rc;
-
-  hipStream_t s = (hipStream_t)hip_stream;
   const int ns = n_stages(q.scheme);
   BatchInst* table = (BatchInst*)ws;
   std::vector<BatchInst> inst(nbatch);
@@ -194,10 +176,64 @@ extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* 
     if (e != hipSuccess) return hip_fail(e, "batched step launch");
     parity ^= 1;
   }
+  return RD_OK;
+}
+
+extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* const* const* fields,
+                               double* const* const* tangents, void* ws, size_t ws_bytes,
+                               void* hip_stream) {
+  const bool tangent = tangents != nullptr;
+  size_t need = 0;
+  int rc = batch_workspace(probs, nbatch, tangent, &need);
+  if (rc) return rc;
+  rc = check_uniform(probs, nbatch);
+  if (rc) return rc;
+  if (!fields) return fail(RD_EINVAL, "fields is NULL");
+  const rd_problem& q = probs[0];
+  const int nv = n_fields(q.model);
+  const int nf = (tangent ? 2 : 1) * nv;
+  for (int32_t i = 0; i < nbatch; ++i) {
+    rc = validate_fields(&probs[i], fields[i], "fields");
+    if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
+    if (tangent) {
+      rc = validate_fields(&probs[i], tangents[i], "tangents");
+      if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
+    }
+  }
+  if (q.nsteps == 0) return RD_OK;
+  if (!ws || ws_bytes < need)
+    return fail(RD_EWORKSPACE, "workspace of %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+  if (((uintptr_t)ws) % 256 != 0) return fail(RD_EINVAL, "workspace is not 256-byte aligned");
+  rc = check_finite_allowed((hipStream_t)hip_stream);
+  if (rc) return rc;
+
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (is_3d(q.stencil)) {
+    // 3-D grids: each instance's stage launches in turn (every instance is
+    // large enough to fill the GPU on its own), bit-identical to rd_step and
+    // rd_jvp on it
+    KConst c;
+    derive_constants(&q, c);
+    char* w = (char*)ws;
+    for (int32_t i = 0; i < nbatch; ++i) {
+      KConst ci = c;
+      ci.nx = probs[i].nx;
+      ci.ny = probs[i].ny;
+      ci.n_total = (double)probs[i].nx;
+      double* a[2 * kMaxFields];
+      for (int f = 0; f < nf; ++f) a[f] = f < nv ? fields[i][f] : tangents[i][f - nv];
+      rc = run_steps_3d(&probs[i], ci, tangent, a, w, q.nsteps, nullptr, 0, s);
+      if (rc) return fail(rc, "problem %d: %s", i, rd_last_error());
+      w += workspace_3d(&probs[i], tangent);
+    }
+  } else {
+    rc = run_batched_2d(probs, nbatch, fields, tangents, ws, s);
+    if (rc) return rc;
+  }
   if (check_finite_bytes()) {
     char* flag = (char*)ws + (need - check_finite_bytes());
     for (int32_t i = 0; i < nbatch; ++i) {
-      const size_t cells = (size_t)probs[i].nx * (size_t)probs[i].ny;
+      const size_t cells = (size_t)probs[i].nx * (size_t)probs[i].ny * (size_t)(is_3d(q.stencil) ? probs[i].nz : 1);
       double* arrs[2 * kMaxFields];
       for (int f = 0; f < nv; ++f) {
         arrs[f] = fields[i][f];

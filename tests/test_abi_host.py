@@ -188,7 +188,9 @@ def test_3d_problems_validated_before_any_device_work():
     cp, _b = p.to_c()
     v, r = C.c_int32(), C.c_int32()
     assert B.lib().rd_get_plan(C.byref(cp), 0, C.byref(v), C.byref(r)) == -2
-    assert B.lib().rd_step_batched_workspace_bytes(C.byref(cp), 1, 0, C.byref(C.c_size_t())) == -2
+    bb = C.c_size_t()
+    assert B.lib().rd_step_batched_workspace_bytes(C.byref(cp), 1, 0, C.byref(bb)) == 0
+    assert bb.value == rd.workspace_bytes(p, "step")   # one instance: its own stage workspace
     # rejected before any launch: no checkpoint spacing, no planes
     fake = (C.c_void_p * 3)(1 << 16, 2 << 16, 3 << 16)
     for kw in ({"checkpoint_every": 0}, {"nz": 0}):

@@ -198,10 +198,27 @@ def test_3d_step_graph_replays():
         assert all(np.array_equal(a, b) for a, b in zip(host(z), host(zr))), rep
 
 
-def test_3d_batches_are_rejected():
-    _, pr, z0 = setup("fk", "lap19", "rk4", 20, 8, 5, 2)
-    with pytest.raises(rd.RDError):
-        rd.step_batched([pr], [dev(z0)])
+@pytest.mark.parametrize("model,stencil,scheme", [("fk", "lap27", "rk4"), ("bocf", "lap19", "rush_larsen"),
+                                                  ("fhn", "lap7", "heun")])
+@pytest.mark.parametrize("tangent", [False, True])
+def test_3d_batched_equals_single_bitwise(model, stencil, scheme, tangent):
+    sizes = [(20, 8, 5), (70, 21, 13), (1, 3, 9), (64, 4, 2)]
+    cases = []
+    for k, (nx, ny, nz) in enumerate(sizes):
+        _, pr, z0 = setup(model, stencil, scheme, nx, ny, nz, 4, seed=k)
+        cases.append((pr, z0, ri.direction(len(z0), nx, ny, 60 + k, nz=nz)))
+    fields = [dev(z0) for _, z0, _ in cases]
+    tans = [dev(v) for _, _, v in cases] if tangent else None
+    rd.step_batched([pr for pr, _, _ in cases], fields, tans)
+    for k, (pr, z0, v) in enumerate(cases):
+        zs, vs = dev(z0), dev(v)
+        if tangent:
+            rd.jvp(pr, zs, vs)
+        else:
+            rd.step(pr, zs)
+        assert all(np.array_equal(a, b) for a, b in zip(host(fields[k]), host(zs))), k
+        if tangent:
+            assert all(np.array_equal(a, b) for a, b in zip(host(tans[k]), host(vs))), k
 
 
 def gpu_vjp(pr, z0, lam):
