@@ -346,6 +346,12 @@ def other_workloads(rd, torch, dev, only=None):
         p.nsteps = n
         sec = _timed(torch, stream, lambda: rd.step(p, z), reps=2)
         cells = w["nx"] * w["ny"] * w["nz"]
+        # tangent (exact JVP) over the same 20 steps
+        v = [torch.from_numpy(a).to(dev) for a in ri.direction(3, w["nx"], w["ny"], 4200, nz=w["nz"])]
+        pj = rd.Problem.from_workload(w, ri.params_array("fk"), nsteps=n)
+        rd.jvp(pj, [t.clone() for t in z], [t.clone() for t in v])
+        sec_jvp = _timed(torch, stream, lambda: rd.jvp(pj, z, v))
+        del v
         # adjoint over the same 20 steps, checkpoints every 10
         p.checkpoint_every = 10
         ck = torch.empty(rd.checkpoint_count(p) * 3 * cells, dtype=torch.float64, device=dev)
@@ -356,6 +362,8 @@ def other_workloads(rd, torch, dev, only=None):
         out["fk_256cube_lap27_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
                                        "hbm_bytes_per_cell_update": STAGE3_RK4_FIELDS * 3 * 8,
                                        "hbm_frac": STAGE3_RK4_FIELDS * 3 * 8 * cells * n / sec / HBM_PEAK,
+                                       "jvp_us_per_step": sec_jvp / n * 1e6,
+                                       "jvp_over_forward": sec_jvp / sec,
                                        "vjp_us_per_step": sec_vjp / n * 1e6,
                                        "vjp_over_forward_with_checkpoints": sec_vjp / sec_ck}
         del z, ck, lam
