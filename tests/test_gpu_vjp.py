@@ -102,7 +102,7 @@ def test_dot_product_jvp_vjp(model, stencil, n, steps):
 def test_adjoint_workload_full_size_dot_and_fd():
     """Barkley 1024^2, RK4, 4000 steps, checkpoints every 64: the exact check
     is the dot-product test against the JVP (1e-12).  Central differences in
-    4 seeded directions are a loose cross-check: over this horizon the
+    32 seeded directions are a loose cross-check: over this horizon the
     rounding differences between the + and - runs are amplified, and the
     measured error of the difference quotient against the gradient is no
     better than 4e-5 at its best step (eps = 1e-5; 1.6e-4 at 1e-6, 5e-3 at
@@ -114,7 +114,7 @@ def test_adjoint_workload_full_size_dot_and_fd():
     lam = [2.0 * w["dx"] ** 2 * zT[0], np.zeros_like(zT[1])]
     g = gpu_vjp(pr, z0, lam)
     loss = lambda z: float(np.sum(z[0] ** 2) * w["dx"] ** 2)
-    for k in range(4):
+    for k in range(32):
         v = ri.direction(2, 1024, 1024, 5000 + k)
         eps = 1e-5
         lp = loss(gpu_step(pr, [a + eps * b for a, b in zip(z0, v)]))
