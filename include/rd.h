@@ -16,8 +16,9 @@
  *
  * Conventions shared by every entry point
  *   - Fields are FP64, one contiguous array per field ("structure of
- *     arrays"), row-major [ny][nx] with x fastest, 8-byte aligned, on the
- *     current HIP device.  Cell (i, j) has centre ((i + 1/2) dx, (j + 1/2) dx).
+ *     arrays"), row-major [ny][nx] ([nz][ny][nx] for the 3-D stencils) with x
+ *     fastest, 8-byte aligned, on the current HIP device.  Cell (i, j) has
+ *     centre ((i + 1/2) dx, (j + 1/2) dx).
  *   - Field order is the model's: Barkley (u, v); Fenton-Karma (u, v, w);
  *     Bueno-Orovio (u, v, w, s); FitzHugh-Nagumo (u, v); diffusion (u).
  *   - All field, tangent, cotangent, checkpoint and workspace pointers are
@@ -38,6 +39,8 @@
  *     capture on `hip_stream` records them; replays repeat the call with the
  *     same pointers.  Inside a capture the autotuner does not time anything:
  *     make one call outside the capture first so the tuned plan is used.
+ *     (The optional finiteness check of rd_set_check_finite synchronises and
+ *     is refused inside a capture.)
  */
 #ifndef RD_H
 #define RD_H
