@@ -132,8 +132,12 @@ __device__ __forceinline__ Dual operator/(Dual a, double b) { return Dual(a.v / 
 //
 // exp: Cody-Waite argument reduction x = n ln2 + r, |r| <= ln2/2, with ln2
 // split into a high part whose product with n is exact and a low part, then
-// the Taylor series of e^r to degree 13 (truncation < 1e-17 relative) by
-// Horner's rule in fused multiply-adds, scaled by 2^n.  About 2 ulp; 20 FP64
+// e^r ~ 1 + r + r^2/2 + r^3 h(r) with h of degree 8, its coefficients the
+// minimax fit of the relative error on |r| <= ln2/2 by the Remez exchange
+// algorithm (exp_poly_fit.py beside this file; approximation error 2.4e-17,
+// the low-order coefficients 1, 1, 1/2 kept exact so that they are inline
+// operands), by Horner's rule in fused multiply-adds, scaled by 2^n.  The
+// polynomial evaluates within 0.6 ulp in double; about 2 ulp in all; 18 FP64
 // operations against ~40 for the general library routine.
 //
 // recip: the hardware reciprocal estimate refined by two Newton-Raphson
@@ -145,17 +149,15 @@ __device__ __forceinline__ double exp_lean(double x) {
   const double n = __builtin_rint(x * 1.4426950408889634);   // log2(e)
   double r = fma(-n, 6.93147180369123816490e-01, x);        // ln2 high part (exact product)
   r = fma(-n, 1.90821492927058770002e-10, r);                // ln2 low part
-  double p = 1.0 / 6227020800.0;                             // 1/13!
-  p = fma(p, r, 1.0 / 479001600.0);
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
+  double p = 2.2976443849446772e-08;  // r^11 ... r^3: the minimax coefficients
+  p = fma(p, r, 2.7622226153978235e-07);
+  p = fma(p, r, 2.7563857293242605e-06);
+  p = fma(p, r, 2.4801516346798477e-05);
+  p = fma(p, r, 1.9841262673010967e-04);
+  p = fma(p, r, 1.3888888920512005e-03);
+  p = fma(p, r, 8.3333333365280360e-03);
+  p = fma(p, r, 4.1666666666619970e-02);
+  p = fma(p, r, 1.6666666666661958e-01);
   p = fma(p, r, 0.5);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
@@ -521,6 +523,21 @@ __device__ __forceinline__ Column make_column(int gx, const KConst& c, bool anis
   return col;
 }
 
+// Eq. (6) with one cross-lane exchange.  With the vertical second difference
+// s = N + S - 2C of each column and r = C + s/6, the 9-point operator times
+// dx^2 is
+//   a_ax (W + E + N + S - 4C) + a_dg (NW + NE + SW + SE - 4C)
+//     = (r_W + r_E - 2C) + (2/3) s,
+// using a_ax + 2 a_dg = 1: only r crosses lanes (two shifts instead of four),
+// and a constant field gives exactly zero (s = 0, r = C).
+__device__ __forceinline__ double lap9_vertical(double up, double cen, double dn) {
+  return fma(-2.0, cen, up + dn);  // 2C is exact: one rounding, as a subtraction
+}
+__device__ __forceinline__ double lap9_exchanged(double s, double cen) { return fma(kAlphaDiag, s, cen); }
+__device__ __forceinline__ double lap9_combine(double rw, double re, double s, double cen, double coef) {
+  return coef * fma(kAlphaAxial, s, fma(-2.0, cen, rw + re));
+}
+
 // Diffusion term at row `rho` of this lane's column, given the values `up`
 // (row rho-1), `cen` (row rho) and `dn` (row rho+1), already mirrored in y
 // (up = cen at rho = 0, dn = cen at rho = ny-1).  All lanes of the wave must
@@ -536,14 +553,12 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
     if (EDGE && col.east) e = cen;
     return coef * (((w + e) + (up + dn)) - 4.0 * cen);
   } else if constexpr (STENCIL == RD_LAP9) {
-    const double cs = up + dn;  // N + S of this column
-    double w = from_west(cen), e = from_east(cen);
-    double ws = from_west(cs), es = from_east(cs);  // NW + SW, NE + SE
-    if (EDGE && col.west) { w = cen; ws = cs; }
-    if (EDGE && col.east) { e = cen; es = cs; }
-    const double axial = ((w + e) + cs) - 4.0 * cen;
-    const double diag = (ws + es) - 4.0 * cen;
-    return coef * (kAlphaAxial * axial + kAlphaDiag * diag);
+    const double s = lap9_vertical(up, cen, dn);
+    const double r = lap9_exchanged(s, cen);
+    double rw = from_west(r), re = from_east(r);
+    if (EDGE && col.west) rw = r;
+    if (EDGE && col.east) re = r;
+    return lap9_combine(rw, re, s, cen, coef);
   } else {
     // Conservative flux form: x-face fluxes shared with the west neighbour
     // through a lane shuffle, y-face fluxes recomputed by both rows with the
@@ -582,11 +597,10 @@ __device__ __forceinline__ double diffusion_rows(const double* up, const double*
   if constexpr (STENCIL == RD_LAP5) {
     return coef * (((cen[iw] + cen[ie]) + (up[il] + dn[il])) - 4.0 * C);
   } else if constexpr (STENCIL == RD_LAP9) {
-    const double cs = up[il] + dn[il];
-    const double ws = up[iw] + dn[iw], es = up[ie] + dn[ie];
-    const double axial = ((cen[iw] + cen[ie]) + cs) - 4.0 * C;
-    const double diag = (ws + es) - 4.0 * C;
-    return coef * (kAlphaAxial * axial + kAlphaDiag * diag);
+    // r of the neighbour columns, computed as those lanes compute their own
+    const double rw = lap9_exchanged(lap9_vertical(up[iw], cen[iw], dn[iw]), cen[iw]);
+    const double re = lap9_exchanged(lap9_vertical(up[ie], cen[ie], dn[ie]), cen[ie]);
+    return lap9_combine(rw, re, lap9_vertical(up[il], C, dn[il]), C, coef);
   } else {
     const double u = up[il], d = dn[il];
     double fxe = col.dxx_e * (cen[il + 1] - C) + col.dxy_e4 * ((dn[il + 1] + d) - (up[il + 1] + u));

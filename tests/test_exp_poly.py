@@ -1,0 +1,101 @@
+"""The device exponential (exp_lean in rd_device.h), evaluated on the host.
+
+Its constants are read from the kernel header and its steps -- clamp, Cody-Waite
+reduction with a two-part ln2, the polynomial by Horner's rule in fused
+multiply-adds, scaling by 2^n -- are replayed with correctly rounded FMAs, then
+compared with mpmath's exponential.  A second check re-runs the Remez fit the
+coefficients come from."""
+import math
+import os
+import random
+import re
+import sys
+
+import mpmath as mp
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "..", "paper_1309_1720_amd", "csrc")
+NUM = r"([-+]?[0-9.]+(?:e[-+]?[0-9]+)?)"
+
+
+def exp_lean_source() -> str:
+    with open(os.path.join(CSRC, "rd_device.h")) as fh:
+        src = fh.read()
+    start = src.index("__device__ __forceinline__ double exp_lean(double x)")
+    return src[start:src.index("\n}\n", start)]
+
+
+def constants():
+    body = exp_lean_source()
+    clamp = float(re.search(r"fmax\(x, -" + NUM + r"\), " + NUM, body).group(2))
+    log2e = float(re.search(r"rint\(x \* " + NUM, body).group(1))
+    hi, lo = (float(v) for v in re.findall(r"fma\(-n, " + NUM, body))
+    first = float(re.search(r"double p = " + NUM, body).group(1))
+    steps = [float(v) for v in re.findall(r"p = fma\(p, r, " + NUM + r"\)", body)]
+    return clamp, log2e, hi, lo, [first] + steps
+
+
+def fma(a: float, b: float, c: float) -> float:
+    with mp.workdps(80):
+        return float(mp.mpf(a) * mp.mpf(b) + mp.mpf(c))
+
+
+def exp_emulated(x: float) -> float:
+    clamp, log2e, hi, lo, coeffs = constants_cached
+    x = min(max(x, -clamp), clamp)
+    n = float(round(x * log2e))  # round half to even, as rint
+    r = fma(-n, hi, x)
+    r = fma(-n, lo, r)
+    p = coeffs[0]
+    for c in coeffs[1:]:
+        p = fma(p, r, c)
+    try:
+        return math.ldexp(p, int(n))
+    except OverflowError:  # the hardware scaling returns infinity
+        return math.inf
+
+
+constants_cached = constants()
+
+
+def ulp_error(x: float) -> float:
+    got = exp_emulated(x)
+    with mp.workdps(40):
+        ref = mp.exp(mp.mpf(x))
+        return float(abs(mp.mpf(got) - ref) / (mp.mpf(2) ** (mp.floor(mp.log(ref, 2)) - 52)))
+
+
+def test_header_coefficients_count_and_low_order_terms():
+    coeffs = constants_cached[4]
+    assert len(coeffs) == 12  # degree 11
+    assert coeffs[-3:] == [0.5, 1.0, 1.0]
+
+
+def test_exp_within_two_ulp_over_the_reaction_range():
+    rng = random.Random(20131309)
+    xs = [rng.uniform(-40.0, 40.0) for _ in range(1500)]
+    xs += [rng.uniform(-700.0, 700.0) for _ in range(300)]
+    # reduced arguments at and near the ends of |r| <= ln2/2, and n = 0
+    xs += [k * math.log(2) + d for k in (-3, 0, 5) for d in (-0.3465, -1e-9, 0.0, 1e-9, 0.3465)]
+    worst = max((ulp_error(x), x) for x in xs)
+    assert worst[0] <= 2.0, worst
+
+
+def test_exp_of_zero_and_saturation():
+    assert exp_emulated(0.0) == 1.0
+    # the clamp keeps n in int range; e^x has long saturated there
+    assert exp_emulated(-1.0e6) == 0.0 and exp_emulated(-800.0) == 0.0
+    assert exp_emulated(1.0e6) == math.inf and exp_emulated(800.0) == math.inf
+
+
+def test_coefficients_are_the_committed_remez_fit():
+    sys.path.insert(0, CSRC)
+    try:
+        import exp_poly_fit
+    finally:
+        sys.path.remove(CSRC)
+    h, worst = exp_poly_fit.fit()
+    assert float(worst) < 3e-17
+    fitted = [float(c) for c in reversed(h)]  # r^11 first, as the header
+    assert constants_cached[4][:9] == fitted

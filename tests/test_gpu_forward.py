@@ -53,8 +53,11 @@ def test_every_combination_matches_oracle(model, stencil, scheme, variant):
     err = rel_linf(got, ref)
     print(f"{variant} {model} {stencil} {scheme}: rel-Linf {err:.3e}")
     assert err <= TOL
-    if model in ("diffusion", "barkley", "fhn") and stencil != "lap9_aniso":
+    if model in ("diffusion", "barkley", "fhn") and stencil == "lap5":
         # same operations in the same order, no library math: bit-identical
+        # (the kernels take Eq. (6) in an equal form with one cross-lane
+        # exchange, and the flux form in their own order, so those two
+        # operators agree with the oracle to rounding only)
         assert all(np.array_equal(g, r) for g, r in zip(got, ref))
 
 

