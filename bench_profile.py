@@ -150,13 +150,15 @@ def main(out: str, tile_rows: int) -> None:
     print(json.dumps(rec, indent=1))
 
 
-STAGE3_KINDS = [  # (template tail, role, arrays read, arrays written), three fields each
-    ("false, false, false, 0>", "stage 1: reads z, writes k1", 1, 1),
-    ("false, true, false, 0>", "stages 2, 3: read z and k_{s-1}, write k_s", 2, 1),
-    ("false, true, true, 0>", "stage 4: reads z, k1, k2, k3, writes z'", 4, 1),
-    ("true, false, true>", "adjoint stage 4: reads z, k3, lambda, writes Ybar, zbar", 3, 2),
-    ("true, true, true>", "adjoint stages 3, 2: read z, k, lambda, Ybar, zbar, write Ybar, zbar", 5, 2),
-    ("false, true, false>", "adjoint stage 1: reads z, lambda, Ybar, zbar, writes lambda_n", 4, 1),
+STAGE3_KINDS = [  # (kernel, template tail, role, arrays read, arrays written), three fields each
+    ("stage3d_kernel", "false, false, false, 0>", "stage 1: reads z, writes k1", 1, 1),
+    ("stage3d_kernel", "false, true, false, 0>", "stages 2, 3: read z and k_{s-1}, write k_s", 2, 1),
+    ("stage3d_kernel", "false, true, true, 0>", "stage 4: reads z, k1, k2, k3, writes z'", 4, 1),
+    ("adjoint3d_kernel", "true, false, true, 0>", "adjoint stage 4: reads z, k3, lambda, writes Ybar, zbar", 3, 2),
+    ("adjoint3d_kernel", "true, true, true, 0>",
+     "adjoint stages 3, 2: read z, k, lambda, Ybar, zbar, write Ybar, zbar", 5, 2),
+    ("adjoint3d_kernel", "false, true, false, 0>", "adjoint stage 1: reads z, lambda, Ybar, zbar, writes lambda_n",
+     4, 1),
 ]
 
 
@@ -180,9 +182,8 @@ def main_3d(out: str) -> None:
              "| kernel | role | calls | avg us | algorithmic GB/s | of 8 TB/s | HBM bytes / algorithmic |",
              "|---|---|---|---|---|---|---|"]
     per = {}
-    for tail, role, nr, nw in STAGE3_KINDS:
-        row = [r for r in stats if ("stage3d" in r["Name"] if "0>" in tail else "adjoint3d" in r["Name"])
-               and r["Name"].split("(")[0].endswith(tail)]
+    for kern, tail, role, nr, nw in STAGE3_KINDS:
+        row = [r for r in stats if kern in r["Name"] and r["Name"].split("(")[0].endswith(tail)]
         if not row:
             continue
         r = row[0]
@@ -192,10 +193,11 @@ def main_3d(out: str) -> None:
         fk = [v for (k, c), v in fetch.items() if k.split("(")[0].replace("void ", "") == name]
         wk = [v for (k, c), v in write.items() if k.split("(")[0].replace("void ", "") == name]
         ratio = (fk[0] * fs + wk[0] * wsc) * 1024 / alg if fk and wk else float("nan")
-        per[tail] = avg
+        per[(kern, tail)] = avg
         lines.append(f"| `{name}` | {role} | {r['Calls']} | {avg:.1f} | {alg / avg / 1e3:.0f} | "
                      f"{alg / avg / 1e3 / 8000 * 100:.0f}% | {ratio:.2f} |")
-    fwd = per["false, false, false, 0>"] + 2 * per["false, true, false, 0>"] + per["false, true, true, 0>"]
+    fwd = (per[("stage3d_kernel", "false, false, false, 0>")] + 2 * per[("stage3d_kernel", "false, true, false, 0>")]
+           + per[("stage3d_kernel", "false, true, true, 0>")])
     lines += ["", f"Forward step (stages 1 + 2 x middle + 4): {fwd:.0f} us = {cells / (fwd * 1e-6):.3e} "
                   f"cell-updates/s, 312 algorithmic bytes per cell-update "
                   f"({312 * cells / (fwd * 1e-6) / 8e12 * 100:.0f}% of 8 TB/s).  A plain device-to-device copy "

@@ -90,9 +90,10 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void adjoint3d_kernel(Adj3Args
         hn = kbar(d, base + hN);
         hs = kbar(d, base + hS);
       }
+      const double cs = vn + vs;
       U[slot][d] = vc;
-      F[slot][d] = (west(vc, hc) + east(vc, hc)) + (vn + vs);
-      if constexpr (DIAG) G[slot][d] = (west(vn, hn) + east(vn, hn)) + (west(vs, hs) + east(vs, hs));
+      F[slot][d] = (west(vc, hc) + east(vc, hc)) + cs;
+      if constexpr (DIAG) G[slot][d] = west(cs, hn + hs) + east(cs, hn + hs);
     }
   };
 

@@ -134,9 +134,11 @@ __global__ __launch_bounds__(kStage3Waves* kWave) void stage3d_kernel(Stage3Args
         hn = yval(f, base + hN);
         hs = yval(f, base + hS);
       }
+      // the in-plane diagonals are the x-neighbours' N + S: one exchange
+      const double cs = yn + ys;
       U[slot][d] = yc;
-      F[slot][d] = (west(yc, hc) + east(yc, hc)) + (yn + ys);
-      if constexpr (DIAG) G[slot][d] = (west(yn, hn) + east(yn, hn)) + (west(ys, hs) + east(ys, hs));
+      F[slot][d] = (west(yc, hc) + east(yc, hc)) + cs;
+      if constexpr (DIAG) G[slot][d] = west(cs, hn + hs) + east(cs, hn + hs);
     }
   };
 
