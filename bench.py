@@ -135,6 +135,9 @@ def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
     e1.record(stream)
     torch.cuda.synchronize()
     jvp_ms = e0.elapsed_time(e1) / steps
+    jvp_rows = rd.get_tile_rows(p, "jvp")
+    # algorithmic bytes: read and write the state and its tangent once
+    jvp_bytes = 4 * len(z0_np) * 8
     # accuracy over a short horizon: FD error relative to the exact JVP
     horizon = 100
     p = rd.Problem.from_workload(w, params, nsteps=horizon)
@@ -153,7 +156,9 @@ def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
         rd.step(p, zm)
         fd = (torch.cat([t.flatten() for t in zp]) - torch.cat([t.flatten() for t in zm])) / (2 * eps)
         errs[f"{eps:.0e}"] = float(torch.linalg.norm(fd - jv) / torch.linalg.norm(jv))
-    return {"ms_per_step": jvp_ms, "over_forward": jvp_ms / fwd_ms,
+    return {"ms_per_step": jvp_ms, "over_forward": jvp_ms / fwd_ms, "tile_rows": jvp_rows,
+            "hbm_bytes_per_cell_update": jvp_bytes,
+            "hbm_frac": nx * ny * jvp_bytes / (jvp_ms * 1e-3) / HBM_PEAK,
             "fd_jvp_ms_per_step": 2 * fwd_ms, "fd_rel_err_by_eps": errs,
             "fd_best_rel_err": min(errs.values()), "horizon_steps": horizon,
             "timed_steps": steps}

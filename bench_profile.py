@@ -26,6 +26,13 @@ barkley_8192_rk4_beyond_llc` (OUT/stats with the kernel trace, OUT/fetch,
 OUT/write):
 
        python bench_profile.py --barkley8192 OUT
+
+The exact tangent step (rd_jvp) of the Fenton-Karma workload from three runs
+of `bench.py --steps 200 --warmup 2 --no-cpu-baseline --no-other-workloads
+--variant sweep --tile-rows T` (T the tangent's band height; OUT/stats,
+OUT/fetch, OUT/write as above):
+
+       python bench_profile.py --tangent OUT T
 """
 from __future__ import annotations
 
@@ -249,10 +256,63 @@ def main_barkley8192(out: str) -> None:
     print("\n".join(lines))
 
 
+TANGENT_KERNEL = "rd::sweep_kernel<2, 9, 4, 1, 1, 0>"
+
+
+def main_tangent(out: str, tile_rows: int) -> None:
+    """The exact tangent step (rd_jvp) of the same workload: OUT/stats with
+    the kernel trace, OUT/fetch and OUT/write with the counters, each a run of
+    `bench.py` at the tangent's band height (which fixes the forward's too)."""
+    cells = 1024 * 1024
+    alg = 4 * 3 * 8 * cells  # read and write the state and its tangent once
+    cmd = lambda extra: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o tan -- "
+                         f"python3 <repo>/bench.py --steps 200 --warmup 2 --no-cpu-baseline --no-other-workloads "
+                         f"--variant sweep --tile-rows {tile_rows}")
+    stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
+    row = [r for r in stats if r["Name"].startswith("void " + TANGENT_KERNEL)]
+    if not row:
+        raise RuntimeError("no tangent kernel in the trace")
+    r = row[0]
+    # the first launches run while the clocks ramp up: use the median dispatch
+    trace = [t for t in _rows(os.path.join(out, "stats"), "*kernel_trace.csv")
+             if t["Kernel_Name"].startswith("void " + TANGENT_KERNEL)]
+    durs = sorted((int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) / 1e3 for t in trace)
+    avg = durs[len(durs) // 2]
+    fetch = _counters(os.path.join(out, "fetch"))
+    write = _counters(os.path.join(out, "write"))
+    f_k, w_k = _pick(fetch, TANGENT_KERNEL, "FETCH_SIZE"), _pick(write, TANGENT_KERNEL, "WRITE_SIZE")
+    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.json")) as fh:
+        cal = json.load(fh)["calibration"]
+    fs, wsc = cal["fetch_scale"], cal["write_scale"]
+    hbm = (f_k * fs + w_k * wsc) * 1024
+    lines = ["# Exact tangent step (rd_jvp), Fenton-Karma 1024x1024 (9-point, RK4, FP64)", "",
+             "Commands (each a run of its own), then `python3 <repo>/bench_profile.py --tangent <out> "
+             f"{tile_rows}`:", "",
+             "    " + cmd("--kernel-trace --stats"), "    " + cmd("--pmc FETCH_SIZE"), "    " + cmd("--pmc WRITE_SIZE"),
+             "", f"Band height {tile_rows} rows (the autotuner's choice for the tangent on this grid).", "",
+             "| kernel | calls | median us | mean us | min us | max us | algorithmic GB/s (median) | of 8 TB/s | "
+             "HBM bytes / algorithmic |",
+             "|---|---|---|---|---|---|---|---|---|",
+             f"| `{TANGENT_KERNEL}` | {r['Calls']} | {avg:.2f} | {float(r['AverageNs']) / 1e3:.2f} | "
+             f"{float(r['MinNs']) / 1e3:.2f} | "
+             f"{float(r['MaxNs']) / 1e3:.2f} | {alg / avg / 1e3:.0f} | {alg / avg / 1e3 / 8000 * 100:.0f}% | "
+             f"{hbm / alg:.2f} |", "",
+             f"Algorithmic bytes per launch: {alg / 1e6:.1f} MB (96 per cell-update: the three fields and their "
+             f"tangents read and written once). Counters per dispatch: FETCH_SIZE {f_k:.0f} KiB, WRITE_SIZE "
+             f"{w_k:.0f} KiB, scaled by {fs:.3f} and {wsc:.3f} (the plain-copy calibration of "
+             f"`profiles/fwd_fk_1024_rk4_counters.md`): {hbm / 1e6:.1f} MB. The step runs at "
+             f"{cells / (avg * 1e-6):.3e} tangent cell-updates/s."]
+    with open(os.path.join(PROFILES, "tan_fk_1024_rk4_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "--barkley8192":
         main_barkley8192(sys.argv[2])
     elif sys.argv[1] == "--stage3d":
         main_3d(sys.argv[2])
+    elif sys.argv[1] == "--tangent":
+        main_tangent(sys.argv[2], int(sys.argv[3]))
     else:
         main(sys.argv[1], int(sys.argv[2]))
