@@ -1,10 +1,15 @@
 """Benchmark: FP64 cell-updates/s of the fused explicit step on one MI355X.
 
-Workload: Fenton-Karma 3-variable model on a 1024 x 1024 grid, isotropic
-9-point Laplacian (Eq. 6), classical RK4, dx = 0.025 cm, dt = 0.1 ms,
-D = 0.001 cm^2/ms, broken-wave spiral seed.  One benchmark "step" is one RK4
-time step of the whole grid (one fused kernel launch).  Inputs are resident
-in HBM before the timed region; the state is advanced in place.
+Headline workload: the Bueno-Orovio 4-variable model (Eq. 5) on a 2048 x 2048
+grid, anisotropic diffusion tensor (D_par = 0.001171, D_perp = D_par / 4
+cm^2/ms, fibre angle rotating linearly from -60 to +60 degrees across x) in
+conservative flux form, classical RK4, dx = 0.025 cm, dt = 0.05 ms, seeded
+multi-spiral initial condition -- the largest single-grid workload.  One
+benchmark "step" is one RK4 time step of the whole grid (one fused kernel
+launch).  Inputs are resident in HBM before the timed region; the state is
+advanced in place.  The K timed steps are taken as REPEATS windows of exactly
+K steps each (HIP events on the launch stream, synchronised on both sides);
+the reported rate is the median window, with the spread.
 
 Prints one JSON line (see the keys below).  --gpus N with N > 1 exits: this
 build runs on a single GPU.
@@ -33,7 +38,18 @@ KERNEL_SOURCES = ["paper_1309_1720_amd/csrc/rd_device.h", "paper_1309_1720_amd/c
 # equations as evaluated (9-point stencil 11, reaction 51 + one exp, stage
 # updates; each add, multiply, divide and exp counts 1).
 FK_RK4_FLOPS = 295
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "fwd_fk_1024_rk4_counters.json")
+# Algorithmic HBM bytes per cell-update of one step: read and write the state
+# once, 2 n_v 8 bytes.
+B_ALG = {"diffusion": 16, "barkley": 32, "fhn": 32, "fk": 48, "bocf": 64}
+HEADLINE = "bocf_2048_aniso_rk4"
+HEADLINE_NAME = "bueno_orovio_2048x2048_lap9_aniso_rk4"
+REPEATS = 5
+MODEL_NAMES = {"diffusion": "diffusion", "barkley": "Barkley", "fhn": "FitzHugh-Nagumo", "fk": "Fenton-Karma",
+               "bocf": "Bueno-Orovio (epicardial)"}
+
+
+def counters_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"fwd_{workload}_counters.json")
 
 
 def kernel_hash() -> str:
@@ -44,29 +60,24 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_counters(cells: int, tile_rows: int):
-    """The committed counter record, if it was taken on the current kernel
-    sources with the band height in use; else None."""
-    if not os.path.exists(COUNTERS_FILE):
+def committed_counters(workload: str):
+    """The committed counter record of ``workload``'s fused step if it was
+    taken on the current kernel sources, else None."""
+    path = counters_file(workload)
+    if not os.path.exists(path):
         return None
-    with open(COUNTERS_FILE) as fh:
+    with open(path) as fh:
         c = json.load(fh)
-    if c.get("kernel_sha") != kernel_hash() or c.get("cells") != cells or c.get("tile_rows") != tile_rows:
+    return c if c.get("kernel_sha") == kernel_hash() else None
+
+
+def measured_counters(workload: str, cells: int, tile_rows: int):
+    """The committed counter record, if it was taken on the current kernel
+    sources, this grid and the band height in use; else None."""
+    c = committed_counters(workload)
+    if c is None or c.get("cells") != cells or c.get("tile_rows") != tile_rows:
         return None
     return c
-
-
-def measured_traffic(cells: int, tile_rows: int):
-    """HBM bytes per launch from committed rocprofv3 counters, if they were
-    taken on the current kernel sources with the band height in use; else
-    None."""
-    if not os.path.exists(COUNTERS_FILE):
-        return None
-    with open(COUNTERS_FILE) as fh:
-        c = json.load(fh)
-    if c.get("kernel_sha") != kernel_hash() or c.get("cells") != cells or c.get("tile_rows") != tile_rows:
-        return None
-    return c.get("hbm_bytes_per_launch")
 
 
 # Vector-instruction issue capacity: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
@@ -74,10 +85,9 @@ def measured_traffic(cells: int, tile_rows: int):
 VALU_LANE_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def valu_issue(cells: int, tile_rows: int, launch_s: float):
-    """Measured lane-instructions per second of the fused step (counter
+def valu_issue(c, launch_s: float):
+    """Lane-instructions per second of the fused step (committed counter
     record x the live launch time) against the issue capacity."""
-    c = measured_counters(cells, tile_rows)
     if not c or "valu_instructions_per_launch" not in c:
         return None
     achieved = c["valu_instructions_per_launch"] * 64 / launch_s
@@ -86,9 +96,77 @@ def valu_issue(cells: int, tile_rows: int, launch_s: float):
             "lane_instructions_per_cell_update": c["lane_instructions_per_cell_update"]}
 
 
-def cpu_baseline(w, params, seconds: float):
-    """The oracle as it stands, on the host, over a bounded number of steps."""
-    import numpy as np
+def windows(torch, stream, fn, reps: int = REPEATS) -> list:
+    """Device seconds of fn() between two events on ``stream``, ``reps``
+    windows, each synchronised on both sides."""
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / 1e3)
+    return out
+
+
+def median(xs):
+    ys = sorted(xs)
+    n = len(ys)
+    return ys[n // 2] if n % 2 else 0.5 * (ys[n // 2 - 1] + ys[n // 2])
+
+
+def window_stats(secs, steps: int) -> dict:
+    med = median(secs)
+    return {"windows": len(secs), "steps_per_window": steps,
+            "us_per_step_median": med / steps * 1e6, "us_per_step_min": min(secs) / steps * 1e6,
+            "us_per_step_max": max(secs) / steps * 1e6, "spread": (max(secs) - min(secs)) / med}
+
+
+def forward_run(rd, torch, dev, name: str, steps: int, warmup: int, reps: int = REPEATS,
+                tile_rows: int = 0, **over):
+    """Times ``reps`` windows of exactly ``steps`` fused steps of workload
+    ``name`` (state resident on the device, advanced in place) after
+    ``warmup`` untimed steps.  Returns (record, final state)."""
+    import rd_inputs as ri
+    w = ri.workload(name, **over)
+    model = w["model"]
+    cells = w["nx"] * w["ny"]
+    params = ri.params_array(model)
+    z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
+    if tile_rows:
+        rd.set_tile_rows(tile_rows)
+    try:
+        p = rd.Problem.from_workload(w, params, nsteps=max(warmup, 1), checkpoint_every=0)
+        rd.step(p, z)   # warm-up; the first call tunes the plan
+        torch.cuda.synchronize()
+        p.nsteps = steps
+        stream = torch.cuda.current_stream(dev)
+        secs = windows(torch, stream, lambda: rd.step(p, z), reps)
+        variant, rows = rd.get_plan(p, "step")
+        k = rd.get_steps_per_launch(p)
+    finally:
+        if tile_rows:
+            rd.set_tile_rows(0)
+    st = window_stats(secs, steps)
+    sec = median(secs)
+    launch_s = sec / steps * k
+    b_alg = B_ALG[model]
+    rec = {"workload": name, "nx": w["nx"], "ny": w["ny"], "model": model, "stencil": w["stencil"],
+           "scheme": w["scheme"], "rate": cells * steps / sec, "us_per_step": st["us_per_step_median"],
+           "timing": st, "plan": [variant, rows], "steps_per_launch": k,
+           "hbm_bytes_per_cell_update": b_alg, "algorithmic_bytes_per_launch": b_alg * cells * k,
+           "avg_launch_us": launch_s * 1e6, "hbm_frac": b_alg * cells * steps / sec / HBM_PEAK}
+    c = measured_counters(name, cells, rows) if variant == "sweep" else None
+    rec["traffic"] = c["hbm_bytes_per_launch"] if c else None
+    rec["valu_issue"] = valu_issue(c, launch_s)
+    return rec, z
+
+
+def cpu_baseline(w, params, seconds: float, label: str):
+    """The oracle as it stands, on the host, over a bounded number of steps
+    of the same workload (whole grid)."""
     import oracle
     import rd_inputs as ri
     po = oracle.Problem.from_workload(w, params=params)
@@ -110,8 +188,8 @@ def cpu_baseline(w, params, seconds: float):
         pass
     return {"value": rate, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "host_cpu": cpu, "host_threads": os.cpu_count(),
-            "sample": f"{n} RK4 steps of the {w['nx']}x{w['ny']} Fenton-Karma grid "
-                      f"(NumPy, single thread), {el:.1f} s"}
+            "sample": f"{n} {w['scheme'].upper()} steps of the whole {w['nx']}x{w['ny']} {label} grid "
+                      f"after one warm-up step (NumPy, single thread), {el:.1f} s"}
 
 
 def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
@@ -128,13 +206,7 @@ def jvp_report(rd, torch, w, params, z0_np, fwd_ms, steps, dev):
     p = rd.Problem.from_workload(w, params, nsteps=20)
     rd.jvp(p, z, v)
     p.nsteps = steps
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    rd.jvp(p, z, v)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    jvp_ms = e0.elapsed_time(e1) / steps
+    jvp_ms = median(windows(torch, stream, lambda: rd.jvp(p, z, v), 3)) * 1e3 / steps
     jvp_rows = rd.get_tile_rows(p, "jvp")
     # algorithmic bytes: read and write the state and its tangent once
     jvp_bytes = 4 * len(z0_np) * 8
@@ -178,12 +250,103 @@ def _timed(torch, stream, fn, reps=1):
     return best
 
 
-def other_workloads(rd, torch, dev, only=None):
-    """Timings of the other workloads (rates in cell-updates/s, device time);
-    ``only`` names one of them to run alone."""
+def ensemble_report(rd, torch, dev, nsteps: int):
+    """The ensemble workload as specified: 64 Fenton-Karma instances (16 each
+    of 256^2 .. 768^2) with seeded unit directions, the forward flow plus the
+    exact JVP over ``nsteps`` RK4 steps (T = 200 ms at 2000 steps) in one
+    batched call per launch sequence, timed end to end; forward-only and
+    per-instance calls for comparison; a graph replay; and central
+    finite-difference JVPs at the same horizon for eps = 1e-9 .. 1e-5."""
+    import rd_inputs as ri
+    stream = torch.cuda.current_stream(dev)
+    ws = ri.fk_batch_workloads(nsteps=2)
+    params = ri.params_array("fk")
+    probs = [rd.Problem.from_workload(x, params) for x in ws]
+    z0 = [ri.fk_ic(x["nx"], x["ny"], x["seed"]) for x in ws]
+    v0 = [ri.direction(3, x["nx"], x["ny"], x["direction_seed"]) for x in ws]
+    to_dev = lambda zs: [[torch.from_numpy(a).to(dev) for a in z] for z in zs]
+    fields, tans = to_dev(z0), to_dev(v0)
+    rd.step_batched(probs, fields, tans)      # first calls tune the band height
+    rd.step_batched(probs, fields, None)
+    for q, f, t in zip(probs, fields, tans):
+        rd.jvp(q, f, t)
+    torch.cuda.synchronize()
+    cells = sum(x["nx"] * x["ny"] for x in ws)
+    out = {"members": len(ws), "cells": cells}
+    # short windows: per-step cost of the batched JVP, forward and per-instance calls
+    n = 20
+    for q in probs:
+        q.nsteps = n
+    sec_b = median(windows(torch, stream, lambda: rd.step_batched(probs, fields, tans)))
+    sec_f = median(windows(torch, stream, lambda: rd.step_batched(probs, fields, None)))
+
+    def per_instance():
+        for q, f, t in zip(probs, fields, tans):
+            rd.jvp(q, f, t)
+    sec_s = median(windows(torch, stream, per_instance, 3))
+    gstream = torch.cuda.Stream(dev)
+    gstream.wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gstream):
+        with torch.cuda.graph(graph, stream=gstream):
+            rd.step_batched(probs, fields, tans)
+    stream.wait_stream(gstream)
+    sec_g = median(windows(torch, stream, graph.replay, 3))
+    del graph
+    out.update({"window_steps": n, "rate_jvp": cells * n / sec_b, "rate_forward": cells * n / sec_f,
+                "jvp_over_forward": sec_b / sec_f, "per_instance_calls_over_batched": sec_s / sec_b,
+                "rate_jvp_graph_replay": cells * n / sec_g, "hbm_frac_jvp": 96 * cells * n / sec_b / HBM_PEAK})
+    # the whole flow over the horizon, from the seeded initial states
+    for q in probs:
+        q.nsteps = nsteps
+    fields, tans = to_dev(z0), to_dev(v0)
+    sec_T = windows(torch, stream, lambda: rd.step_batched(probs, fields, tans), 1)[0]
+    fwd = to_dev(z0)
+    sec_Tf = windows(torch, stream, lambda: rd.step_batched(probs, fwd, None), 1)[0]
+    if not all(bool(torch.equal(a, b)) for fa, fb in zip(fields, fwd) for a, b in zip(fa, fb)):
+        raise RuntimeError("ensemble: the JVP run's state differs from the forward run's")
+    del fwd
+    jv = [torch.cat([t.flatten() for t in tl]) for tl in tans]
+    fd_err = {}
+    for k in range(9, 4, -1):
+        eps = 10.0 ** (-k)
+        zp = to_dev([[a + eps * b for a, b in zip(z, v)] for z, v in zip(z0, v0)])
+        zm = to_dev([[a - eps * b for a, b in zip(z, v)] for z, v in zip(z0, v0)])
+        rd.step_batched(probs, zp, None)
+        rd.step_batched(probs, zm, None)
+        errs = []
+        for i in range(len(ws)):
+            fd = (torch.cat([t.flatten() for t in zp[i]]) - torch.cat([t.flatten() for t in zm[i]])) / (2 * eps)
+            errs.append(float(torch.linalg.norm(fd - jv[i]) / torch.linalg.norm(jv[i])))
+        fd_err[f"{eps:.0e}"] = {"median": median(errs), "max": max(errs), "min": min(errs)}
+        del zp, zm
+    best = min(fd_err, key=lambda e: fd_err[e]["median"])
+    out.update({"horizon_steps": nsteps, "horizon_ms": nsteps * ws[0]["dt"],
+                "flow_and_jvp_seconds": sec_T, "forward_flow_seconds": sec_Tf,
+                "flow_jvp_over_forward": sec_T / sec_Tf,
+                "rate_jvp_horizon": cells * nsteps / sec_T,
+                "fd_jvp_seconds": 2 * sec_Tf,
+                "fd_rel_err_by_eps": fd_err, "fd_best_eps": best,
+                "fd_best_median_rel_err": fd_err[best]["median"]})
+    return out
+
+
+def other_workloads(rd, torch, dev, only=None, steps: int = 200):
+    """Timings of the other workloads (rates in cell-updates/s, device time,
+    median of REPEATS windows where a window is cheap); ``only`` names one of
+    them to run alone."""
     import rd_inputs as ri
     stream = torch.cuda.current_stream(dev)
     out = {}
+
+    if only in (None, "fk_1024_rk4"):
+        # Fenton-Karma 1024^2, 9-point, RK4 (the workload of the tangent record)
+        rec, _ = forward_run(rd, torch, dev, "fk_1024_rk4", steps, 20)
+        rec["roofline_alu"] = {"bound": "alu", "achieved": FK_RK4_FLOPS * rec["rate"] / 1e12,
+                               "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                               "frac": FK_RK4_FLOPS * rec["rate"] / FP64_VECTOR_PEAK,
+                               "flops_per_cell_update": FK_RK4_FLOPS}
+        out["fk_1024_rk4"] = rec
 
     if only in (None, "barkley_128_euler_1000"):
         # Barkley 128^2, 5-point, Euler, 1000 steps (whole run)
@@ -192,7 +355,7 @@ def other_workloads(rd, torch, dev, only=None):
         p = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=20)
         rd.step(p, z)
         p.nsteps = w["nsteps"]
-        sec = _timed(torch, stream, lambda: rd.step(p, z))
+        sec = median(windows(torch, stream, lambda: rd.step(p, z)))
         # the same 1000 steps captured once in a HIP graph and replayed (no
         # per-launch host overhead)
         gstream = torch.cuda.Stream(dev)
@@ -202,7 +365,7 @@ def other_workloads(rd, torch, dev, only=None):
             with torch.cuda.graph(graph, stream=gstream):
                 rd.step(p, z)
         stream.wait_stream(gstream)
-        sec_g = _timed(torch, stream, graph.replay, reps=3)
+        sec_g = median(windows(torch, stream, graph.replay))
         out["barkley_128_euler_1000"] = {"seconds": sec, "rate": 128 * 128 * w["nsteps"] / sec,
                                          "steps_per_launch": rd.get_steps_per_launch(p),
                                          "us_per_step": sec / w["nsteps"] * 1e6,
@@ -218,7 +381,7 @@ def other_workloads(rd, torch, dev, only=None):
         p = rd.Problem.from_workload(w, ri.params_array("fhn"), nsteps=8)
         rd.step(p, z)
         p.nsteps = w["nsteps"]
-        sec = _timed(torch, stream, lambda: rd.step(p, z))
+        sec = median(windows(torch, stream, lambda: rd.step(p, z)))
         cells = w["nx"] * w["ny"]
         out["fhn_256_rk4_1000"] = {"seconds": sec, "rate": cells * w["nsteps"] / sec,
                                    "us_per_step": sec / w["nsteps"] * 1e6,
@@ -226,91 +389,29 @@ def other_workloads(rd, torch, dev, only=None):
                                    "plan": list(rd.get_plan(p, "step")),
                                    "hbm_frac": 32 * cells * w["nsteps"] / sec / HBM_PEAK}
 
-    if only in (None, "bocf_2048_aniso_rk4"):
-        # Bueno-Orovio 2048^2, anisotropic flux form, RK4 (50 of its 5000 steps)
-        w = ri.workload("bocf_2048_aniso_rk4")
-        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-        p = rd.Problem.from_workload(w, ri.params_array("bocf"), nsteps=4)
-        rd.step(p, z)
-        n = 50
-        p.nsteps = n
-        sec = _timed(torch, stream, lambda: rd.step(p, z))
-        cells = w["nx"] * w["ny"]
-        out["bocf_2048_aniso_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
-                                      "plan": list(rd.get_plan(p, "step")),
-                                      "hbm_frac": 64 * cells * n / sec / HBM_PEAK}
-
     if only in (None, "fk_4096_rk4_beyond_llc"):
         # Beyond the 256 MB last-level cache: Fenton-Karma 4096^2 (3 x 128 MiB per
         # state), the same scheme, so the traffic really goes to HBM.
-        w = ri.workload("fk_1024_rk4", nx=4096, ny=4096)
-        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-        p = rd.Problem.from_workload(w, ri.params_array("fk"), nsteps=2)
-        rd.step(p, z)
-        n = 20
-        p.nsteps = n
-        sec = _timed(torch, stream, lambda: rd.step(p, z))
-        cells = w["nx"] * w["ny"]
-        out["fk_4096_rk4_beyond_llc"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
-                                         "hbm_frac": 48 * cells * n / sec / HBM_PEAK,
-                                         "plan": list(rd.get_plan(p, "step"))}
+        rec, z = forward_run(rd, torch, dev, "fk_1024_rk4", 20, 2, reps=3, nx=4096, ny=4096)
+        rec["workload"] = "fk_4096_rk4_beyond_llc"
+        out["fk_4096_rk4_beyond_llc"] = rec
         del z
 
     if only in (None, "barkley_8192_rk4_beyond_llc"):
         # HBM-bound 2-D probe beyond the 256 MB last-level cache: Barkley
         # 8192^2 (1 GiB per state), 5-point, RK4, steps per launch tuned.
-        w = ri.workload("barkley_1024_rk4_adjoint", nx=8192, ny=8192, checkpoint_every=0)
-        z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
-        p = rd.Problem.from_workload(w, ri.params_array("barkley"), nsteps=4)
-        rd.step(p, z)
-        n = 16
-        p.nsteps = n
-        sec = _timed(torch, stream, lambda: rd.step(p, z), reps=2)
-        cells = w["nx"] * w["ny"]
-        out["barkley_8192_rk4_beyond_llc"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
-                                              "steps_per_launch": rd.get_steps_per_launch(p),
-                                              "hbm_bytes_per_cell_update": 32,
-                                              "hbm_frac": 32 * cells * n / sec / HBM_PEAK}
+        rec, z = forward_run(rd, torch, dev, "barkley_1024_rk4_adjoint", 16, 4, reps=3, nx=8192, ny=8192)
+        rec["workload"] = "barkley_8192_rk4_beyond_llc"
+        out["barkley_8192_rk4_beyond_llc"] = rec
         del z
 
-    if only in (None, "fk_ensemble_64_jvp"):
-        # Ensemble: 64 Fenton-Karma grids (16 each of 256^2 .. 768^2) with tangents
-        ws = ri.fk_batch_workloads(nsteps=2)
-        params = ri.params_array("fk")
-        probs = [rd.Problem.from_workload(x, params) for x in ws]
-        fields = [[torch.from_numpy(a).to(dev) for a in ri.fk_ic(x["nx"], x["ny"], x["seed"])] for x in ws]
-        tans = [[torch.from_numpy(a).to(dev) for a in ri.direction(3, x["nx"], x["ny"], x["direction_seed"])]
-                for x in ws]
-        rd.step_batched(probs, fields, tans)      # first calls tune the band height
-        rd.step_batched(probs, fields, None)
-        for q, f, t in zip(probs, fields, tans):
-            rd.jvp(q, f, t)
-        torch.cuda.synchronize()
-        n = 20
-        for q in probs:
-            q.nsteps = n
-        cells = sum(x["nx"] * x["ny"] for x in ws)
-        sec_b = _timed(torch, stream, lambda: rd.step_batched(probs, fields, tans), reps=3)
-        sec_f = _timed(torch, stream, lambda: rd.step_batched(probs, fields, None), reps=3)
+    if only in (None, "barkley_1024_rk4"):
+        # the adjoint workload's forward step alone (no checkpoints)
+        rec, _ = forward_run(rd, torch, dev, "barkley_1024_rk4_adjoint", steps, 20)
+        out["barkley_1024_rk4"] = rec
 
-        def per_instance():
-            for q, f, t in zip(probs, fields, tans):
-                rd.jvp(q, f, t)
-        sec_s = _timed(torch, stream, per_instance, reps=3)
-        # the same batched call captured once in a HIP graph and replayed
-        gstream = torch.cuda.Stream(dev)
-        gstream.wait_stream(stream)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.stream(gstream):
-            with torch.cuda.graph(graph, stream=gstream):
-                rd.step_batched(probs, fields, tans)
-        stream.wait_stream(gstream)
-        sec_g = _timed(torch, stream, graph.replay, reps=3)
-        out["fk_ensemble_64_jvp"] = {"steps": n, "cells": cells, "rate_jvp": cells * n / sec_b,
-                                     "rate_forward": cells * n / sec_f, "jvp_over_forward": sec_b / sec_f,
-                                     "per_instance_calls_over_batched": sec_s / sec_b,
-                                     "rate_jvp_graph_replay": cells * n / sec_g,
-                                     "hbm_frac_jvp": 96 * cells * n / sec_b / HBM_PEAK}
+    if only in (None, "fk_ensemble_64_jvp"):
+        out["fk_ensemble_64_jvp"] = ensemble_report(rd, torch, dev, 2000)
 
     if only in (None, "newton_krylov_fhn_3_members_200_steps"):
         # Newton-Krylov fixed points of the 200-step FitzHugh-Nagumo flow for a
@@ -342,14 +443,14 @@ def other_workloads(rd, torch, dev, only=None):
 
     if only in (None, "fk_256cube_lap27_rk4"):
         # 3-D: Fenton-Karma 256^3, 27-point, RK4 (20 of its 1000 steps), one
-        # HBM-bound launch per stage (STAGE3_RK4_FIELDS arrays per field and cell).
+        # HBM-streaming launch per stage (STAGE3_RK4_FIELDS arrays per field and cell).
         w = ri.workload("fk_256cube_lap27_rk4")
         z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(w)]
         p = rd.Problem.from_workload(w, ri.params_array("fk"), nsteps=2)
         rd.step(p, z)
         n = 20
         p.nsteps = n
-        sec = _timed(torch, stream, lambda: rd.step(p, z), reps=2)
+        sec = median(windows(torch, stream, lambda: rd.step(p, z), 3))
         cells = w["nx"] * w["ny"] * w["nz"]
         # tangent (exact JVP) over the same 20 steps
         v = [torch.from_numpy(a).to(dev) for a in ri.direction(3, w["nx"], w["ny"], 4200, nz=w["nz"])]
@@ -364,9 +465,12 @@ def other_workloads(rd, torch, dev, only=None):
         lam = [t.clone() for t in z]
         rd.vjp(p, ck, [t.clone() for t in z])
         sec_vjp = _timed(torch, stream, lambda: rd.vjp(p, ck, lam))
+        stream_bytes = STAGE3_RK4_FIELDS * 3 * 8
         out["fk_256cube_lap27_rk4"] = {"steps": n, "rate": cells * n / sec, "us_per_step": sec / n * 1e6,
-                                       "hbm_bytes_per_cell_update": STAGE3_RK4_FIELDS * 3 * 8,
-                                       "hbm_frac": STAGE3_RK4_FIELDS * 3 * 8 * cells * n / sec / HBM_PEAK,
+                                       "hbm_bytes_per_cell_update": B_ALG["fk"],
+                                       "hbm_frac": B_ALG["fk"] * cells * n / sec / HBM_PEAK,
+                                       "stage_stream_bytes_per_cell_update": stream_bytes,
+                                       "stage_stream_frac": stream_bytes * cells * n / sec / HBM_PEAK,
                                        "jvp_us_per_step": sec_jvp / n * 1e6,
                                        "jvp_over_forward": sec_jvp / sec,
                                        "vjp_us_per_step": sec_vjp / n * 1e6,
@@ -395,16 +499,20 @@ def other_workloads(rd, torch, dev, only=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=REPEATS,
+                    help="timed windows of exactly --steps steps each; the median is reported")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--variant", choices=["sweep", "pipe"], default=None)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jvp", action="store_true")
     ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--only-workload", default=None,
                     help="run only this one of the other workloads and print its record")
+    ap.add_argument("--workload", default=HEADLINE,
+                    help="single-grid 2-D workload timed as the headline (profiling runs)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -417,11 +525,6 @@ def main():
     import paper_1309_1720_amd as rd
     import rd_inputs as ri
 
-    w = ri.workload("fk_1024_rk4")
-    params = ri.params_array("fk")
-    nx, ny = w["nx"], w["ny"]
-    cells = nx * ny
-    nv = ri.N_FIELDS["fk"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.only_workload:
@@ -430,48 +533,37 @@ def main():
             raise SystemExit(f"bench.py: unknown workload {args.only_workload!r}")
         print(json.dumps(rec))
         return
-    z0_np = ri.initial_condition(w)
-    z = [torch.from_numpy(a).to(dev) for a in z0_np]
+
+    name = args.workload
+    w = ri.workload(name)
+    if w["nz"] != 1:
+        raise SystemExit(f"bench.py: {name} is not a 2-D workload")
+    params = ri.params_array(w["model"])
+    nx, ny = w["nx"], w["ny"]
+    cells = nx * ny
+    nv = ri.N_FIELDS[w["model"]]
     plan_source = "autotuned"
-    if args.tile_rows:
-        rd.set_tile_rows(args.tile_rows)
+    tile_rows = args.tile_rows
+    if tile_rows:
         plan_source = "--tile-rows"
     elif args.variant is None:
         # Run at the band height the committed counter profile was taken at
         # (when it matches the kernel sources), so that the traffic figure
-        # describes this very launch; the autotuner's own choice for this
-        # grid is within about 1% of it.
-        if os.path.exists(COUNTERS_FILE):
-            with open(COUNTERS_FILE) as fh:
-                c = json.load(fh)
-            if c.get("kernel_sha") == kernel_hash() and c.get("cells") == cells:
-                rd.set_tile_rows(int(c["tile_rows"]))
-                plan_source = "band height of the committed counter profile"
+        # describes this very launch.
+        c = committed_counters(name)
+        if c and c.get("cells") == cells:
+            tile_rows = int(c["tile_rows"])
+            plan_source = "band height of the committed counter profile"
     if args.variant:
         rd.set_kernel_variant(args.variant)
-    p = rd.Problem.from_workload(w, params, nsteps=args.warmup)
-    if args.warmup:
-        rd.step(p, z)
-    torch.cuda.synchronize()
-
-    p.nsteps = args.steps
-    stream = torch.cuda.current_stream(dev)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    rd.step(p, z)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    rec, z = forward_run(rd, torch, dev, name, args.steps, args.warmup, args.repeats, tile_rows)
     wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1)
-    sec = ms / 1e3
     if not all(bool(torch.isfinite(t).all()) for t in z):
         raise RuntimeError("non-finite state after the timed steps")
-
-    variant, tile_rows = rd.get_plan(p, "step")
-    if plan_source != "autotuned":
-        rd.set_tile_rows(0)  # the other measurements use their own tuned plans
+    del z
+    if args.variant:
+        rd.set_kernel_variant(None)
     if args.calibration_copy:
         # a plain elementwise copy of 2^26 doubles (512 MiB read + 512 MiB written)
         src = torch.rand(1 << 26, dtype=torch.float64, device=dev)
@@ -480,48 +572,48 @@ def main():
             torch.add(src, 0.0, out=dst)
         torch.cuda.synchronize()
 
-    rate = cells * args.steps / sec
-    bytes_per_launch = 2 * nv * 8 * cells  # read and write the state once
-    launch_s = sec / args.steps            # one fused kernel per step
-    achieved = bytes_per_launch / launch_s
+    variant, rows = rec["plan"]
+    launch_s = rec["avg_launch_us"] * 1e-6
+    achieved = rec["algorithmic_bytes_per_launch"] / launch_s
     out = {
         "metric": "FP64 cell-updates/s",
-        "value": rate,
+        "value": rec["rate"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": rec["us_per_step"] / 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "fenton_karma_1024x1024_lap9_rk4", "nx": nx, "ny": ny,
-                   "stencil": "lap9", "scheme": "rk4", "dx": w["dx"], "dt": w["dt"],
-                   "D": w["D_par"], "fields": nv},
+        "config": {"workload": HEADLINE_NAME if name == HEADLINE else name, "nx": nx, "ny": ny,
+                   "model": MODEL_NAMES[w["model"]], "stencil": w["stencil"], "scheme": w["scheme"],
+                   "dx": w["dx"], "dt": w["dt"], "D_par": w["D_par"], "D_perp": w["D_perp"],
+                   "theta_deg": [round(math.degrees(w["theta0"])), round(math.degrees(w["theta1"]))],
+                   "fields": nv},
+        "timing": rec["timing"],
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": measured_traffic(cells, tile_rows) if variant == "sweep" else None,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "avg_launch_us": launch_s * 1e6},
-        "roofline_alu": {"bound": "alu", "achieved": FK_RK4_FLOPS * rate / 1e12,
-                         "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                         "frac": FK_RK4_FLOPS * rate / FP64_VECTOR_PEAK,
-                         "flops_per_cell_update": FK_RK4_FLOPS},
-        "valu_issue": valu_issue(cells, tile_rows if variant == "sweep" else -1, launch_s),
+                     "traffic": rec["traffic"],
+                     "algorithmic_bytes_per_launch": rec["algorithmic_bytes_per_launch"],
+                     "avg_launch_us": rec["avg_launch_us"]},
+        "valu_issue": rec["valu_issue"],
         "kernel_variant": variant,
-        "tile_rows": tile_rows,
+        "tile_rows": rows,
         "plan_source": plan_source,
         "wall_s": wall,
     }
     if not args.no_jvp:
-        out["jvp"] = jvp_report(rd, torch, w, params, z0_np, ms / args.steps,
-                                min(args.steps, 1000), dev)
+        wf = ri.workload("fk_1024_rk4")
+        fk, _ = forward_run(rd, torch, dev, "fk_1024_rk4", 200, 20, 3)
+        out["jvp"] = jvp_report(rd, torch, wf, ri.params_array("fk"), ri.initial_condition(wf),
+                                fk["us_per_step"] / 1e3, 200, dev)
     if not args.no_other_workloads:
         out["other_workloads"] = other_workloads(rd, torch, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, params, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, params, args.cpu_seconds, MODEL_NAMES[w["model"]])
     print(json.dumps(out), flush=True)
 
 

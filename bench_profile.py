@@ -1,18 +1,19 @@
 """Condense rocprofv3 output of the benchmark's fused step into the summaries
 under profiles/ (text only) and the traffic record bench.py reads.
 
-Runs of rocprofv3 (each its own process, from /tmp, band height pinned):
+A 2-D workload's fused step (the headline Bueno-Orovio 2048^2 step, or the
+Fenton-Karma 1024^2 one) from four runs of rocprofv3, each its own process,
+from /tmp, with the band height T pinned:
 
-    rocprofv3 --kernel-trace --stats --output-format csv -d OUT/stats -o fk -- \\
-        python3 REPO/bench.py --steps 4000 --warmup 50 --no-cpu-baseline --no-jvp \\
-        --no-other-workloads --variant sweep --tile-rows T
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o fk -- \\
-        python3 REPO/bench.py --steps 20 --warmup 2 --no-cpu-baseline --no-jvp \\
-        --no-other-workloads --variant sweep --tile-rows T --calibration-copy
+    rocprofv3 --kernel-trace --stats --output-format csv -d OUT/stats -o fwd -- \
+        python3 REPO/bench.py --steps 20 --warmup 5 --workload W --no-cpu-baseline --no-jvp \
+        --no-other-workloads --variant sweep --repeats 1 --tile-rows T
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o fwd -- \
+        (the same bench.py command) --calibration-copy
     (the same with --pmc WRITE_SIZE into OUT/write, and with the SQ counters
-    below into OUT/sq)
+    below into OUT/sq, without the copy)
 
-then:  python bench_profile.py OUT T
+then:  python bench_profile.py --forward OUT W T
 
 The 3-D stage kernels (Fenton-Karma 256^3, 27-point, RK4) from three runs of
 `bench.py --only-workload fk_256cube_lap27_rk4` (kernel trace and stats,
@@ -47,12 +48,11 @@ import bench
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILES = os.path.join(HERE, "profiles")
-KERNEL = "rd::sweep_kernel<2, 9, 4, 0, 1, 0>"
 CALIB = "CUDAFunctorOnSelf_add<double>"
 CALIB_BYTES = 1 << 29  # 2^26 doubles read and the same written
 SQ_COUNTERS = ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
                "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "SQ_INSTS_SALU"]
-BENCH_ARGS = "--no-cpu-baseline --no-jvp --no-other-workloads --variant sweep"
+BENCH_ARGS = "--no-cpu-baseline --no-jvp --no-other-workloads --variant sweep --repeats 1"
 
 
 def _rows(root: str, pattern: str) -> list[dict]:
@@ -78,81 +78,111 @@ def _pick(counters: dict, needle: str, counter: str) -> float:
     return vals[0]
 
 
-def main(out: str, tile_rows: int) -> None:
-    cells = 1024 * 1024
-    alg = 2 * 3 * 8 * cells
-    cmd = lambda extra, steps: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o fk -- "
-                                f"python3 <repo>/bench.py --steps {steps} --warmup {2 if steps == 20 else 50} "
-                                f"{BENCH_ARGS} --tile-rows {tile_rows}")
+MODEL_ID = {"diffusion": 0, "barkley": 1, "fk": 2, "bocf": 3, "fhn": 4}
+STENCIL_ID = {"lap5": 5, "lap9": 9, "lap9_aniso": 10}
+SCHEME_ID = {"euler": 1, "heun": 2, "rk4": 4}
 
-    # kernel timings
+
+def sweep_kernel(w: dict) -> str:
+    """Name prefix of the fused state sweep of a 2-D workload."""
+    return (f"rd::sweep_kernel<{MODEL_ID[w['model']]}, {STENCIL_ID[w['stencil']]}, "
+            f"{SCHEME_ID[w['scheme']]}, 0, ")
+
+
+def _trace_durations(root: str, needle: str) -> list:
+    rows = [t for t in _rows(root, "*kernel_trace.csv") if needle in t["Kernel_Name"]]
+    return [(int(t["End_Timestamp"]) - int(t["Start_Timestamp"])) / 1e3 for t in rows]
+
+
+def main_forward(out: str, workload: str, tile_rows: int) -> None:
+    """Kernel timings, HBM traffic and instruction counters of one 2-D
+    workload's fused step, from four runs of bench.py with that workload as
+    the headline at a pinned band height."""
+    import rd_inputs as ri
+    w = ri.workload(workload)
+    cells = w["nx"] * w["ny"]
+    alg = bench.B_ALG[w["model"]] * cells
+    needle = sweep_kernel(w)
+    args = f"--workload {workload} {BENCH_ARGS} --tile-rows {tile_rows}"
+    cmd = lambda extra, steps: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o fwd -- "
+                                f"python3 <repo>/bench.py --steps {steps} --warmup 5 {args}")
+    title = f"{w['model']} {w['nx']}x{w['ny']}, {w['stencil']}, {w['scheme']}"
+
     stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
-    lines = ["# Fused RK4 step, Fenton-Karma 1024x1024 (9-point, FP64) — kernel timings", "",
-             "Command:", "", "    " + cmd("--kernel-trace --stats", 4000), "",
-             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
-    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:6]:
-        name = r["Name"].split("(")[0]
-        lines.append(f"| `{name[:80]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
-                     f"{float(r['Percentage']):.1f} |")
-    main_row = [r for r in stats if r["Name"].startswith("void " + KERNEL)]
-    if main_row:
-        avg = float(main_row[0]["AverageNs"]) / 1e3
-        lines += ["", f"The calls are the warm-up and timed steps, one launch per step; the fused step "
-                      f"averages {avg:.2f} us = {cells / (avg * 1e-6):.3e} cell-updates/s, "
-                      f"{alg / (avg * 1e-6) / 1e9:.0f} GB/s algorithmic."]
-    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_kernel_stats.md"), "w") as fh:
+    row = [r for r in stats if needle in r["Name"]]
+    if len(row) != 1:
+        raise RuntimeError(f"expected one kernel matching {needle!r}, found {len(row)}")
+    r = row[0]
+    kname = r["Name"].split("(")[0].replace("void ", "")
+    durs = _trace_durations(os.path.join(out, "stats"), needle)
+    avg = float(r["AverageNs"]) / 1e3
+    med = sorted(durs)[len(durs) // 2]
+    lines = [f"# Fused step, {title} (FP64) — kernel timings", "",
+             "Command:", "", "    " + cmd("--kernel-trace --stats", 20), "",
+             "| kernel | calls | avg us | median us | min us | max us | % of GPU time |",
+             "|---|---|---|---|---|---|---|"]
+    for q in sorted(stats, key=lambda q: -float(q["TotalDurationNs"]))[:6]:
+        name = q["Name"].split("(")[0].replace("void ", "")
+        qd = _trace_durations(os.path.join(out, "stats"), name) or [float("nan")]
+        lines.append(f"| `{name[:80]}` | {q['Calls']} | {float(q['AverageNs']) / 1e3:.2f} | "
+                     f"{sorted(qd)[len(qd) // 2]:.2f} | {float(q['MinNs']) / 1e3:.2f} | "
+                     f"{float(q['MaxNs']) / 1e3:.2f} | {float(q['Percentage']):.1f} |")
+    lines += ["", f"Band height {tile_rows} rows.  The {r['Calls']} calls of `{kname}` are the warm-up and "
+                  f"the timed steps, one launch per step; it averages {avg:.2f} us (median {med:.2f} us) = "
+                  f"{cells / (avg * 1e-6):.3e} cell-updates/s, {alg / (avg * 1e-6) / 1e9:.0f} GB/s of "
+                  f"algorithmic traffic ({bench.B_ALG[w['model']]} B per cell-update: the state read and "
+                  f"written once), {alg / (avg * 1e-6) / bench.HBM_PEAK * 100:.1f}% of 8 TB/s."]
+    with open(os.path.join(PROFILES, f"fwd_{workload}_kernel_stats.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
 
-    # traffic
     fetch = _counters(os.path.join(out, "fetch"))
     write = _counters(os.path.join(out, "write"))
-    f_k, w_k = _pick(fetch, KERNEL, "FETCH_SIZE"), _pick(write, KERNEL, "WRITE_SIZE")
+    f_k, w_k = _pick(fetch, needle, "FETCH_SIZE"), _pick(write, needle, "WRITE_SIZE")
     f_c, w_c = _pick(fetch, CALIB, "FETCH_SIZE"), _pick(write, CALIB, "WRITE_SIZE")
     fs, wsc = CALIB_BYTES / 1024 / f_c, CALIB_BYTES / 1024 / w_c
     hbm = (f_k * fs + w_k * wsc) * 1024
-    rec = {"kernel": KERNEL + " (Fenton-Karma, 9-point, RK4, state)",
-           "workload": "fenton_karma_1024x1024_lap9_rk4", "cells": cells,
+    sq = _counters(os.path.join(out, "sq"))
+    g = {c: _pick(sq, needle, c) for c in SQ_COUNTERS}
+    rec = {"kernel": kname, "workload": workload, "cells": cells,
            "kernel_sha": bench.kernel_hash(), "tile_rows": tile_rows,
+           "avg_launch_us": avg, "median_launch_us": med,
            "fetch_kib_per_dispatch": round(f_k, 1), "write_kib_per_dispatch": round(w_k, 1),
            "calibration": {"kernel": "torch.add(src, 0.0, out=dst), 2^26 doubles",
                            "bytes_read": CALIB_BYTES, "bytes_written": CALIB_BYTES,
                            "fetch_kib": round(f_c, 1), "write_kib": round(w_c, 1),
                            "fetch_scale": fs, "write_scale": wsc},
-           "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg}
-    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.json"), "w") as fh:
-        json.dump(rec, fh, indent=1)
-        fh.write("\n")
-
-    sq = _counters(os.path.join(out, "sq"))
-    g = {c: _pick(sq, KERNEL, c) for c in SQ_COUNTERS}
-    rec["valu_instructions_per_launch"] = g["SQ_INSTS_VALU"]
-    rec["lane_instructions_per_cell_update"] = g["SQ_INSTS_VALU"] * 64 / cells
-    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.json"), "w") as fh:
+           "hbm_bytes_per_launch": hbm, "algorithmic_bytes_per_launch": alg,
+           "valu_instructions_per_launch": g["SQ_INSTS_VALU"],
+           "lane_instructions_per_cell_update": g["SQ_INSTS_VALU"] * 64 / cells,
+           "sq": g}
+    with open(bench.counters_file(workload), "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     waves = g["SQ_WAVES"]
-    lines = ["# Fused RK4 step, Fenton-Karma 1024x1024 — hardware counters", "",
+    lines = [f"# Fused step, {title} — hardware counters", "",
              "Commands (each a run of its own):", "",
              "    " + cmd("--pmc FETCH_SIZE", 20) + " --calibration-copy",
              "    " + cmd("--pmc WRITE_SIZE", 20) + " --calibration-copy",
              "    " + cmd("--pmc " + " ".join(SQ_COUNTERS), 20),
-             "    python3 <repo>/bench_profile.py <out> " + str(tile_rows), "",
+             f"    python3 <repo>/bench_profile.py --forward <out> {workload} {tile_rows}", "",
              "## Memory traffic (KiB per dispatch)", "",
              "| kernel | FETCH_SIZE | WRITE_SIZE |", "|---|---|---|",
-             f"| `{KERNEL}` | {f_k:.1f} | {w_k:.1f} |",
+             f"| `{kname}` | {f_k:.1f} | {w_k:.1f} |",
              f"| calibration copy, 2^26 doubles (512 MiB in, 512 MiB out) | {f_c:.0f} | {w_c:.0f} |", "",
              f"Calibration: FETCH_SIZE is scaled by {fs:.3f} and WRITE_SIZE by {wsc:.3f}. Scaled traffic per "
              f"launch: {f_k * fs:.0f} KiB read + {w_k * wsc:.0f} KiB written = {hbm / 1e6:.1f} MB, against "
-             f"{alg / 1e6:.1f} MB algorithmic (read and write the 3-field state once).", "",
+             f"{alg / 1e6:.1f} MB algorithmic ({hbm / alg:.2f}x).", "",
              "## Instruction and occupancy counters (per dispatch)", "",
              "| counter | value | per wave |", "|---|---|---|"]
     for c in SQ_COUNTERS:
         lines.append(f"| {c} | {g[c]:.4g} | {g[c] / waves:.4g} |")
-    lines += ["", f"Lane-instructions per cell-update: {g['SQ_INSTS_VALU'] * 64 / cells:.0f}. Share of wave "
+    lines += ["", f"Lane-instructions per cell-update: {g['SQ_INSTS_VALU'] * 64 / cells:.0f}. VALU issue "
+                  f"rate at the {avg:.1f} us average launch: "
+                  f"{g['SQ_INSTS_VALU'] * 64 / (avg * 1e-6) / bench.VALU_LANE_ISSUE_PEAK * 100:.0f}% of the "
+                  f"{bench.VALU_LANE_ISSUE_PEAK / 1e12:.1f} T lane-instructions/s capacity. Share of wave "
                   f"time issuing VALU: {g['SQ_ACTIVE_INST_VALU'] / g['SQ_WAVE_CYCLES']:.2f}; waiting on "
                   f"dependencies (memory): {g['SQ_WAIT_INST_ANY'] / g['SQ_WAVE_CYCLES']:.2f}."]
-    with open(os.path.join(PROFILES, "fwd_fk_1024_rk4_counters.md"), "w") as fh:
+    with open(os.path.join(PROFILES, f"fwd_{workload}_counters.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(json.dumps(rec, indent=1))
 
@@ -314,5 +344,7 @@ if __name__ == "__main__":
         main_3d(sys.argv[2])
     elif sys.argv[1] == "--tangent":
         main_tangent(sys.argv[2], int(sys.argv[3]))
+    elif sys.argv[1] == "--forward":
+        main_forward(sys.argv[2], sys.argv[3], int(sys.argv[4]))
     else:
-        main(sys.argv[1], int(sys.argv[2]))
+        raise SystemExit(__doc__)

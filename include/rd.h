@@ -121,8 +121,12 @@ enum rd_stencil {
  * at x = nx dx). */
 enum rd_bc { RD_BC_NOFLUX = 0, RD_BC_PERIODIC = 1 };
 
-/* Operations, for rd_workspace_bytes(). */
-enum rd_op { RD_OP_STEP = 0, RD_OP_JVP = 1, RD_OP_VJP = 2, RD_OP_BATCHED = 3 };
+/* Operations, for rd_workspace_bytes(): rd_step, rd_jvp, rd_vjp, and
+ * rd_step_batched without (RD_OP_BATCHED) or with (RD_OP_BATCHED_JVP)
+ * tangents. */
+enum rd_op {
+  RD_OP_STEP = 0, RD_OP_JVP = 1, RD_OP_VJP = 2, RD_OP_BATCHED = 3, RD_OP_BATCHED_JVP = 4
+};
 
 enum rd_status {
   RD_OK = 0,
@@ -176,8 +180,16 @@ int rd_n_params(int32_t model);
  * [m][field][ny][nx] ([m][field][nz][ny][nx] in 3-D). */
 int rd_checkpoint_count(const rd_problem* p, int64_t* out);
 
-/* Bytes of device workspace `op` needs for problem `p` (for RD_OP_BATCHED,
- * `p` points to `nbatch` problems -- see rd_step_batched_workspace_bytes). */
+/* Bytes of device workspace an operation needs (the problem statement of
+ * Sect. 3 fixes every size).
+ *   RD_OP_STEP, RD_OP_JVP, RD_OP_VJP: for the one problem `p` (rd_step,
+ *     rd_jvp, rd_vjp); *out is only written.
+ *   RD_OP_BATCHED, RD_OP_BATCHED_JVP: for rd_step_batched on the batch
+ *     p[0 .. nbatch-1] without / with tangents.  *out is read first: it must
+ *     hold nbatch (1 <= nbatch <= 65536) on entry, and is overwritten with the
+ *     byte count.  Every problem of the batch is validated.
+ * The counts include the 256 bytes of the finiteness check while it is
+ * enabled.  On error *out is left as it was. */
 int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out);
 
 /*
@@ -230,6 +242,9 @@ int rd_vjp(const rd_problem* p, const double* checkpoints, double* const* cotang
  *   tangents     NULL for a forward-only run, else tangents[b] as in
  *                rd_jvp: the tangents are advanced with the states.
  * Results equal per-problem rd_step / rd_jvp bit for bit.
+ * rd_step_batched_workspace_bytes(probs, nbatch, with_tangents, out) is
+ * rd_workspace_bytes(probs, with_tangents ? RD_OP_BATCHED_JVP :
+ * RD_OP_BATCHED, out) with nbatch passed as an argument.
  */
 int rd_step_batched_workspace_bytes(const rd_problem* probs, int32_t nbatch,
                                     int32_t with_tangents, size_t* out);

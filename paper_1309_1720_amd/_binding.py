@@ -23,7 +23,7 @@ SCHEMES = {"euler": 1, "heun": 2, "rk4": 4, "rush_larsen": 5, "implicit_euler": 
 BCS = {"noflux": 0, "periodic": 1}
 STENCILS = {"lap5": 5, "lap9": 9, "lap9_aniso": 10, "lap7": 7, "lap19": 19, "lap27": 27}
 STENCILS_3D = ("lap7", "lap19", "lap27")
-OPS = {"step": 0, "jvp": 1, "vjp": 2, "batched": 3}
+OPS = {"step": 0, "jvp": 1, "vjp": 2, "batched": 3, "batched_jvp": 4}
 N_FIELDS = {"diffusion": 1, "barkley": 2, "fk": 3, "bocf": 4, "fhn": 2}
 
 STATUS = {0: "RD_OK", -1: "RD_EINVAL", -2: "RD_EUNSUPPORTED", -3: "RD_EWORKSPACE", -4: "RD_EHIP",
@@ -179,15 +179,25 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-# One workspace buffer per (device, stream), grown on demand and reused by
-# later calls on that stream (stream order keeps consecutive calls apart).
+# Eager calls: one workspace buffer per (device, stream), grown on demand and
+# reused by later eager calls on that stream (stream order keeps consecutive
+# calls apart).  Calls made while the stream is being captured into a HIP
+# graph never touch that cache: each gets a buffer of its own, which the graph
+# replays write into, kept alive here until release_workspaces().  So growing
+# the eager buffer never frees memory a graph holds, and eager calls never
+# share a buffer with a graph replayed on another stream.
 _WORKSPACES: dict = {}
+_CAPTURED: list = []
 
 
 def _workspace(nbytes: int, device):
     if nbytes == 0:
         return None, 0
     dev = torch.device(device)
+    if torch.cuda.is_current_stream_capturing():
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        _CAPTURED.append(ws)
+        return ws, ws.data_ptr()
     key = (dev.index if dev.index is not None else torch.cuda.current_device(), _stream(dev))
     ws = _WORKSPACES.get(key)
     if ws is None or ws.numel() < nbytes:
@@ -198,8 +208,11 @@ def _workspace(nbytes: int, device):
 
 
 def release_workspaces() -> None:
-    """Drop the cached workspace buffers (returned to torch's allocator)."""
+    """Drop the cached workspace buffers (returned to torch's allocator),
+    including those of captured calls: replaying a graph captured before this
+    call is then no longer allowed."""
     _WORKSPACES.clear()
+    _CAPTURED.clear()
 
 
 def n_fields(model: str) -> int:
@@ -210,7 +223,17 @@ def n_params(model: str) -> int:
     return _check(lib().rd_n_params(MODELS[model]))
 
 
-def workspace_bytes(prob: Problem, op: str = "step") -> int:
+def workspace_bytes(prob, op: str = "step") -> int:
+    """rd_workspace_bytes: ``prob`` is one Problem for "step", "jvp", "vjp",
+    and the list of a batch's problems for "batched" and "batched_jvp"."""
+    if op in ("batched", "batched_jvp"):
+        probs = list(prob)
+        cps, bufs = zip(*[p.to_c() for p in probs])
+        arr = (_CProblem * len(probs))(*cps)
+        out = C.c_size_t(len(probs))  # nbatch on entry
+        _check(lib().rd_workspace_bytes(arr, OPS[op], C.byref(out)))
+        del bufs
+        return out.value
     cp, _buf = prob.to_c()
     out = C.c_size_t(0)
     _check(lib().rd_workspace_bytes(C.byref(cp), OPS[op], C.byref(out)))
@@ -379,8 +402,8 @@ def step_batched(probs, fields_list, tangents_list=None):
         tptrs = [_ptrs(tl, p, "tangents") for tl, p in zip(tangents_list, probs)]
         tpp = (_DPP * n)(*[C.cast(a, _DPP) for a in tptrs])
     dev = fields_list[0][0].device
-    need = C.c_size_t(0)
-    _check(L.rd_step_batched_workspace_bytes(arr, n, 0 if tangents_list is None else 1, C.byref(need)))
+    need = C.c_size_t(n)  # nbatch on entry
+    _check(L.rd_workspace_bytes(arr, OPS["batched" if tangents_list is None else "batched_jvp"], C.byref(need)))
     ws, wsp = _workspace(need.value, dev)
     _check(L.rd_step_batched(arr, n, fpp, tpp, wsp, need.value, _stream(dev)))
     del bufs

@@ -408,6 +408,14 @@ int rd_checkpoint_count(const rd_problem* p, int64_t* out) {
 }
 
 int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out) {
+  if (op == RD_OP_BATCHED || op == RD_OP_BATCHED_JVP) {
+    // the batch p[0 .. nbatch-1], nbatch read from *out
+    if (!out) return fail(RD_EINVAL, "out is NULL");
+    const size_t n = *out;
+    if (n < 1 || n > 65536)
+      return fail(RD_EINVAL, "batched workspace query: *out must hold nbatch in [1, 65536] on entry, got %zu", n);
+    return batch_workspace(p, (int32_t)n, op == RD_OP_BATCHED_JVP, out);
+  }
   int rc = validate(p);
   if (rc) return rc;
   if (!out) return fail(RD_EINVAL, "out is NULL");
@@ -418,7 +426,6 @@ int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out) {
       case RD_OP_STEP: *out = workspace_3d(p, false) + check_finite_bytes(); return RD_OK;
       case RD_OP_JVP: *out = workspace_3d(p, true) + check_finite_bytes(); return RD_OK;
       case RD_OP_VJP: *out = workspace_vjp_3d(p) + check_finite_bytes(); return RD_OK;
-      case RD_OP_BATCHED: return fail(RD_EUNSUPPORTED, "batches of 3-D grids are not supported");
     }
     return fail(RD_EINVAL, "unknown op %d", op);
   }
@@ -432,8 +439,6 @@ int rd_workspace_bytes(const rd_problem* p, int32_t op, size_t* out) {
       workspace_vjp(p, out);
       *out += check_finite_bytes();
       return RD_OK;
-    case RD_OP_BATCHED:
-      return fail(RD_EINVAL, "use rd_step_batched_workspace_bytes for batched runs");
   }
   return fail(RD_EINVAL, "unknown op %d", op);
 }

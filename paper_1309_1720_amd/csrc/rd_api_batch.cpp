@@ -42,7 +42,7 @@ static size_t table_bytes(int32_t n) { return align_up(sizeof(BatchInst) * (size
 
 // 2-D: the descriptor table and one partner array per instance array.  3-D:
 // each instance's own stage workspace (its grids run one after another).
-static int batch_workspace(const rd_problem* probs, int32_t n, bool tangent, size_t* out) {
+int batch_workspace(const rd_problem* probs, int32_t n, bool tangent, size_t* out) {
   if (!probs) return fail(RD_EINVAL, "problems is NULL");
   if (n < 1 || n > 65536) return fail(RD_EINVAL, "nbatch %d outside [1, 65536]", n);
   size_t total = is_3d(probs[0].stencil) ? 0 : table_bytes(n);
@@ -65,7 +65,10 @@ using namespace rd;
 extern "C" int rd_step_batched_workspace_bytes(const rd_problem* probs, int32_t nbatch,
                                                int32_t with_tangents, size_t* out) {
   if (!out) return fail(RD_EINVAL, "out is NULL");
-  return batch_workspace(probs, nbatch, with_tangents != 0, out);
+  size_t n = nbatch > 0 ? (size_t)nbatch : 0;
+  const int rc = rd_workspace_bytes(probs, with_tangents ? RD_OP_BATCHED_JVP : RD_OP_BATCHED, &n);
+  if (rc == RD_OK) *out = n;
+  return rc;
 }
 
 // The 2-D batch: one descriptor table and one launch per step over all

@@ -235,9 +235,21 @@ __device__ __forceinline__ Dual step_h(Dual x, const KConst& c) {
 // several times more), and without the cancellation 1 + tanh(x) suffers for
 // x << 0.  The caller passes the exponent e = -2x, formed from u by one
 // multiply-add with host-computed constants.
+//
+// The exponent is capped at 700 first.  Beyond it the logistic is below
+// 1e-304 (and (1 + tanh x)/2 rounds to exactly 0 in double), but exp(e) would
+// overflow to +inf from e = 709.8 on, and the reciprocal's Newton step turns
+// 1/inf into inf * 0 = NaN.  Capped, the value stays a positive double below
+// 1e-304 and its derivative is 0, as is the derivative of the rounded
+// (1 + tanh x)/2 there.  Reached only far outside the physiological range
+// (Fenton-Karma u < -34, Bueno-Orovio u < -5.4).
+__device__ __forceinline__ double cap_exponent(double e) { return fmin(e, 700.0); }
+__device__ __forceinline__ Dual cap_exponent(Dual e) {
+  return Dual(fmin(e.v, 700.0), e.v > 700.0 ? 0.0 : e.d);
+}
 template <class T>
 __device__ __forceinline__ T logistic_of_exponent(T e) {
-  return recip(1.0 + exp(e));
+  return recip(1.0 + exp(cap_exponent(e)));
 }
 
 // ---------------------------------------------------------------------------

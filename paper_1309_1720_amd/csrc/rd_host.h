@@ -50,6 +50,8 @@ size_t field_bytes(const rd_problem* p);
 int copy_state(double* const* dst, double* const* src, int nv, size_t bytes, hipStream_t s);
 
 int workspace_jvp(const rd_problem* p, size_t* out);
+// Workspace of rd_step_batched for probs[0 .. n-1] (validates each problem).
+int batch_workspace(const rd_problem* probs, int32_t n, bool tangent, size_t* out);
 
 // Optional finiteness check (rd_check.hip): extra workspace bytes while it is
 // enabled (0 otherwise), and the scan itself (RD_OK when disabled).

@@ -218,3 +218,42 @@ def test_check_finite_knob_adds_workspace():
         rd.set_check_finite(False)
     assert rd.workspace_bytes(p, "step") == base["step"]
     assert B.STATUS[-5] == "RD_ENONFINITE"
+
+
+def test_workspace_bytes_takes_a_batch():
+    """rd_workspace_bytes(p, RD_OP_BATCHED[_JVP], out) sizes rd_step_batched for
+    the batch p[0 .. nbatch-1], nbatch read from *out; the separate
+    rd_step_batched_workspace_bytes is the same query."""
+    sizes = [(64, 48), (33, 17), (100, 7)]
+    probs = [base_problem(nx=nx, ny=ny) for nx, ny in sizes]
+    cps, bufs = zip(*[p.to_c() for p in probs])
+    arr = (B._CProblem * len(probs))(*cps)
+    L = B.lib()
+    for op, tangents in ((3, 0), (4, 1)):
+        out = C.c_size_t(len(probs))
+        assert L.rd_workspace_bytes(arr, op, C.byref(out)) == 0, L.rd_last_error()
+        alias = C.c_size_t(0)
+        assert L.rd_step_batched_workspace_bytes(arr, len(probs), tangents, C.byref(alias)) == 0
+        assert out.value == alias.value
+        # descriptor table (256-byte aligned) + one partner array per instance array
+        fields = sum((1 + tangents) * 3 * (-(-nx * ny * 8 // 256) * 256) for nx, ny in sizes)
+        assert fields < out.value <= fields + 256 * len(probs) + 4096
+        # a prefix of the batch needs less
+        out1 = C.c_size_t(1)
+        assert L.rd_workspace_bytes(arr, op, C.byref(out1)) == 0
+        assert out1.value < out.value
+    assert rd.workspace_bytes(probs, "batched") < rd.workspace_bytes(probs, "batched_jvp")
+    # nbatch out of range on entry, or an invalid member: refused, *out untouched
+    for n in (0, 65537):
+        out = C.c_size_t(n)
+        assert L.rd_workspace_bytes(arr, 3, C.byref(out)) == -1
+        assert out.value == n
+    bad = base_problem(nx=0)
+    cb, _bb = bad.to_c()
+    arr2 = (B._CProblem * 2)(cps[0], cb)
+    out = C.c_size_t(2)
+    assert L.rd_workspace_bytes(arr2, 3, C.byref(out)) == -1
+    assert "problem 1" in L.rd_last_error().decode()
+    assert L.rd_workspace_bytes(arr, 3, None) == -1
+    assert L.rd_workspace_bytes(arr, 9, C.byref(C.c_size_t(1))) == -1
+    del bufs

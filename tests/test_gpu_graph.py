@@ -80,3 +80,33 @@ def test_single_grid_step_with_checkpoints_graph_replays(name, nsteps, every):
         torch.cuda.synchronize()
         assert all(np.array_equal(a, b) for a, b in zip(host(z), host(zr))), rep
         assert torch.equal(ck, ckr), rep
+
+
+def test_captured_workspace_survives_larger_eager_calls_on_the_capture_stream():
+    """Warm up on a side stream, capture on it, then run a larger problem
+    eagerly on that same stream (which grows its cached workspace) and fill
+    fresh allocations with other data; the graph's replays still equal eager
+    runs: a captured call's workspace is its own and is never freed."""
+    w = ri.workload("fk_1024_rk4", nx=150, ny=97)
+    _, pr = problems(w, nsteps=4)
+    _, big = problems(w, nsteps=2, nx=700, ny=500)
+    z0 = ri.initial_condition(w)
+    zb = ri.fk_ic(700, 500, 11)
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        rd.step(pr, dev(z0))          # warm-up on the side stream (tuning, cached workspace)
+        z = dev(z0)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            rd.step(pr, z)
+        zr = dev(z0)
+        for rep in range(REPLAYS):
+            rd.step(big, dev(zb))      # larger workspace needed on this stream
+            junk = torch.full((1 << 22,), float(rep + 1), dtype=torch.float64, device="cuda")
+            rd.step(pr, zr)
+            g.replay()
+            del junk
+            stream.synchronize()
+            assert all(np.array_equal(a, b) for a, b in zip(host(z), host(zr))), rep
+    torch.cuda.current_stream().wait_stream(stream)

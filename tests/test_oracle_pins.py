@@ -786,6 +786,48 @@ def test_one_ulp_perturbation_floor_over_1000_steps(model, name, n):
     assert err <= 1e-12, err
 
 
+@pytest.mark.parametrize("model,stencil", [("barkley", "lap9"), ("barkley", "lap9_aniso"), ("fk", "lap9"),
+                                           ("bocf", "lap9_aniso")])
+def test_adjoint_one_ulp_floor_over_200_steps(model, stencil):
+    """How far rounding moves a long-horizon gradient: the oracle's adjoint of
+    L = dx^2 sum u(T)^2 over 200 RK4 steps (checkpoints every 32), from initial
+    states one ulp apart and the same cotangent, changes by at most 1e-13
+    relative (measured 1e-15 .. 2e-14), two orders below the 1e-11 bar the GPU
+    gradient is held to on these operators and models."""
+    base = {"barkley": "barkley_1024_rk4_adjoint", "fk": "fk_1024_rk4", "bocf": "bocf_2048_aniso_rk4"}[model]
+    w = ri.workload(base, model=model, stencil=stencil, scheme="rk4", nx=48, ny=40)
+    if model == "barkley" and stencil == "lap9_aniso":
+        w.update(D_perp=0.25, theta0=-1.0, theta1=1.0)
+    p = oracle.Problem.from_workload(w, params=ri.params_array(model))
+    z0 = ri.initial_condition(w) if model != "bocf" else ri.bocf_ic(48, 40, 3, amp=1e-2)
+    zT = oracle.step(p, z0, 200)
+    lam = [2.0 * p.dx ** 2 * zT[0]] + [np.zeros_like(a) for a in zT[1:]]
+    g0 = oracle.vjp(p, z0, lam, 200, checkpoint_every=32)
+    g1 = oracle.vjp(p, [np.nextafter(x, np.inf) for x in z0], lam, 200, checkpoint_every=32)
+    err = max(float(np.max(np.abs(x - y)) / np.max(np.abs(y))) for x, y in zip(g1, g0))
+    assert 0.0 < err <= 1e-13, err
+
+
+def test_fhn_rk4_precision_floor_saturates():
+    """Sect. 5 after Table 1: for FitzHugh-Nagumo the relative error of RK4
+    falls at fourth order as dt shrinks until it saturates at the FP64
+    rounding floor (the paper: around 1e-14).  Richardson differences of
+    successive dt halvings (16^2, dx = 0.04, 9-point, T = 0.004) show order 4
+    down to ~1e-14 and then stop falling at ~1e-15."""
+    w = ri.workload("fhn_256_rk4", nx=16, ny=16)
+    z0 = ri.initial_condition(w)
+    sols = []
+    for lv in range(10):
+        dt = 2e-4 / 2 ** lv
+        p = oracle.Problem.from_workload(dict(w, dt=dt), params=ri.params_array("fhn"))
+        sols.append(np.concatenate([a.ravel() for a in oracle.step(p, z0, int(round(0.004 / dt)))]))
+    e = [float(np.linalg.norm(sols[k] - sols[k + 1]) / np.linalg.norm(sols[k + 1])) for k in range(9)]
+    orders = [math.log2(e[k] / e[k + 1]) for k in range(8)]
+    assert all(abs(o - 4.0) < 0.2 for o in orders[:6]), orders
+    assert 1e-16 < min(e) < 1e-14, e          # the floor is reached ...
+    assert e[-1] > 0.5 * e[-2], e              # ... and the error stops falling there
+
+
 def test_fp64_floor_against_long_double():
     """The same FitzHugh-Nagumo run (16 x 16, 9-point, RK4, 200 steps) in
     FP64 and in extended precision differ by no more than the FP64
