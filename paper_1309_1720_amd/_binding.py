@@ -15,7 +15,9 @@ from dataclasses import dataclass, field
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librd.so")
+# RD_LIBRARY selects another build of the same library (the host-sanitised
+# one of build.build_asan, for CPU-only ABI checks).
+LIB_PATH = os.environ.get("RD_LIBRARY") or os.path.join(_HERE, "librd.so")
 ABI_VERSION = 2
 
 MODELS = {"diffusion": 0, "barkley": 1, "fk": 2, "bocf": 3, "fhn": 4}

@@ -696,6 +696,85 @@ def test_periodic_conserves_sum_and_commutes_with_shifts(stencil):
 # Brute force and precision floor
 # ---------------------------------------------------------------------------
 
+def _brute_flux_div(p, a, j, i, rel):
+    """div(rel D grad u) at cell (i, j) of the list-of-rows field a, face by
+    face (Sect. 3 flux form): each of the four face fluxes from its own
+    formula, zero on a boundary face, the cross-derivative terms reading
+    ghost values by the half-sample mirror (index clamped into the grid) or
+    the periodic wrap.  The tensor is D = D_perp I + (D_par - D_perp) f f^T
+    with f = (cos t, sin t), t linear in x: at the x-face between columns k
+    and k + 1, t = theta0 + (theta1 - theta0)(k + 1)/nx; at the centre of
+    column k, t = theta0 + (theta1 - theta0)(k + 1/2)/nx."""
+    ny, nx = p.ny, p.nx
+    periodic = p.bc == "periodic"
+    dd = p.D_par - p.d_perp
+
+    def g(jj, ii):
+        if periodic:
+            return a[jj % ny][ii % nx]
+        return a[min(max(jj, 0), ny - 1)][min(max(ii, 0), nx - 1)]
+
+    def theta(x):
+        return p.theta0 + (p.theta1 - p.theta0) * x / nx
+
+    def xface(k):  # flux through the face between columns k and k + 1, row j
+        if not periodic and (k < 0 or k >= nx - 1):
+            return 0.0
+        t = theta((k % nx if periodic else k) + 1.0)
+        dxx = p.d_perp + dd * math.cos(t) ** 2
+        dxy = dd * math.cos(t) * math.sin(t)
+        du_dx = g(j, k + 1) - g(j, k)
+        du_dy = ((g(j + 1, k + 1) + g(j + 1, k)) - (g(j - 1, k + 1) + g(j - 1, k))) / 4.0
+        return dxx * du_dx + dxy * du_dy
+
+    def yface(m):  # flux through the face between rows m and m + 1, column i
+        if not periodic and (m < 0 or m >= ny - 1):
+            return 0.0
+        t = theta(i + 0.5)
+        dxy = dd * math.cos(t) * math.sin(t)
+        dyy = p.d_perp + dd * math.sin(t) ** 2
+        du_dx = ((g(m + 1, i + 1) + g(m, i + 1)) - (g(m + 1, i - 1) + g(m, i - 1))) / 4.0
+        du_dy = g(m + 1, i) - g(m, i)
+        return dxy * du_dx + dyy * du_dy
+
+    return ((xface(i) - xface(i - 1)) + (yface(j) - yface(j - 1))) * rel / (p.dx * p.dx)
+
+
+@pytest.mark.parametrize("bc", ["noflux", "periodic"])
+@pytest.mark.parametrize("nx,ny", [(5, 4), (1, 3), (3, 1), (2, 2), (6, 7), (1, 1)])
+def test_flux_form_brute_force_face_by_face(nx, ny, bc):
+    """The vectorised anisotropic flux form against scalar face-by-face
+    loops on tiny grids, every cell including edges and corners, where the
+    cross terms read mirrored ghosts and the boundary faces carry no flux."""
+    rng = np.random.default_rng(nx * 31 + ny + (7 if bc == "periodic" else 0))
+    for rep in range(3):
+        th0, th1 = rng.uniform(-1.5, 1.5, 2)
+        p = oracle.Problem(model="diffusion", scheme="euler", stencil="lap9_aniso", nx=nx, ny=ny, dx=0.3,
+                           dt=0.01, D_par=1.3, D_perp=0.2 + 0.3 * rep, theta0=th0, theta1=th1, bc=bc)
+        u = rng.standard_normal((ny, nx))
+        rel = 1.0 if rep < 2 else 1.5
+        got = oracle.lap_aniso(u, p, rel)
+        a = u.tolist()
+        ref = np.array([[_brute_flux_div(p, a, j, i, rel) for i in range(nx)] for j in range(ny)])
+        scale = np.max(np.abs(u)) * 1.5 * 1.3 / 0.09
+        assert np.max(np.abs(got - ref)) <= 1e-14 * scale, (rep, np.max(np.abs(got - ref)))
+
+
+def test_flux_form_brute_force_detects_a_dropped_cross_term():
+    """The face-by-face loops tell the flux form from a variant without the
+    cross-derivative terms at the boundary (a plausible mistake: ghosts
+    ignored), so the pin above is not vacuous."""
+    p = oracle.Problem(model="diffusion", scheme="euler", stencil="lap9_aniso", nx=5, ny=4, dx=0.3, dt=0.01,
+                       D_par=1.3, D_perp=0.2, theta0=-0.7, theta1=0.9)
+    u = np.random.default_rng(5).standard_normal((4, 5))
+    a = u.tolist()
+    ref = np.array([[_brute_flux_div(p, a, j, i, 1.0) for i in range(5)] for j in range(4)])
+    iso = oracle.Problem(model="diffusion", scheme="euler", stencil="lap9_aniso", nx=5, ny=4, dx=0.3, dt=0.01,
+                         D_par=1.3, D_perp=1.3, theta0=-0.7, theta1=0.9)
+    assert np.max(np.abs(oracle.lap_aniso(u, iso) - ref)) > 1e-2
+    assert np.max(np.abs(oracle.lap_aniso(u, p) - ref)) <= 1e-12
+
+
 def _brute_step(p, z, nsteps):
     """The explicit schemes of Sect. 3 as scalar loops over a tiny grid: the
     ghost rule of Fig. 1 (or the periodic wrap) by explicit index
@@ -711,6 +790,8 @@ def _brute_step(p, z, nsteps):
         return a[min(max(j, 0), ny - 1)][min(max(i, 0), nx - 1)]
 
     def lap(a, j, i, c):
+        if p.stencil == "lap9_aniso":
+            return _brute_flux_div(p, a, j, i, c * p.dx * p.dx / p.D_par)
         axial = at(a, j, i - 1) + at(a, j, i + 1) + at(a, j - 1, i) + at(a, j + 1, i) - 4.0 * a[j][i]
         if p.stencil == "lap5":
             return c * axial
@@ -753,16 +834,19 @@ def _brute_step(p, z, nsteps):
 
 
 @pytest.mark.parametrize("model", ["diffusion", "barkley", "fk", "bocf", "fhn"])
-@pytest.mark.parametrize("stencil", ["lap5", "lap9"])
+@pytest.mark.parametrize("stencil", ["lap5", "lap9", "lap9_aniso"])
 @pytest.mark.parametrize("scheme", ["euler", "heun", "rk4"])
 @pytest.mark.parametrize("bc", ["noflux", "periodic"])
 def test_brute_force_scalar_loops_all_models(model, stencil, scheme, bc):
     """The vectorised oracle agrees with scalar loops on a 5 x 4 grid, three
-    steps, to rounding (the loops sum in their own order)."""
+    steps, to rounding (the loops sum in their own order); the flux form with
+    a rotating fibre field, face by face."""
     base = {"diffusion": "fk_1024_rk4", "barkley": "barkley_1024_rk4_adjoint", "fk": "fk_1024_rk4",
             "bocf": "bocf_2048_aniso_rk4", "fhn": "fhn_256_rk4"}[model]
-    w = ri.workload(base, model=model, stencil=stencil, scheme=scheme, nx=5, ny=4, bc=bc,
-                    D_perp=None, theta0=0.0, theta1=0.0)
+    aniso = stencil == "lap9_aniso"
+    w = ri.workload(base, model=model, stencil=stencil, scheme=scheme, nx=5, ny=4, bc=bc)
+    w.update(D_perp=0.3 * w["D_par"] if aniso else None, theta0=-0.8 if aniso else 0.0,
+             theta1=1.1 if aniso else 0.0)
     p = oracle.Problem.from_workload(w, params=ri.params_array(model))
     z = ri.random_fields(model, 5, 4, 11)
     got = oracle.step(p, z, 3)
