@@ -234,10 +234,12 @@ int rd_vjp(const rd_problem* p, const double* checkpoints, double* const* cotang
 
 /*
  * rd_step_batched -- advance `nbatch` independent problems that differ only
- * in their grid sizes (model, scheme, stencil, boundary rule, dx, dt, nsteps,
- * diffusivities, fibre angles and parameters agree; RD_EUNSUPPORTED
- * otherwise) in one launch per step over all of them (an addition to the
- * paper); 3-D instances run their stage launches one instance after another.
+ * in their grid sizes and time steps (model, scheme, stencil, boundary rule,
+ * dx, nsteps, diffusivities, fibre angles and parameters agree;
+ * RD_EUNSUPPORTED otherwise) in one launch per step over all of them (an
+ * addition to the paper: ensembles, Krylov directions, and periodic orbits
+ * whose periods T_i = nsteps dt_i differ); 3-D instances run their stage
+ * launches one instance after another.
  *   fields[b]    host array of n_fields device pointers of problem b.
  *   tangents     NULL for a forward-only run, else tangents[b] as in
  *                rd_jvp: the tangents are advanced with the states.

@@ -12,4 +12,4 @@ from ._binding import (  # noqa: F401
     step_batched, vec_gram, vec_lincomb, vjp, workspace_bytes,
 )
 from .autograd import RDFlow, flow  # noqa: F401,E402
-from .krylov import gmres_lockstep, newton_krylov  # noqa: F401,E402
+from .krylov import gmres_lockstep, newton_krylov, periodic_orbit  # noqa: F401,E402

@@ -190,19 +190,19 @@ void derive_constants(const rd_problem* p, KConst& c) {
       m.dtau_vm = q[7] - q[6];
       m.inv_tau_vp = 1.0 / q[8];
       m.tau_w1m = q[9];
-      m.dtau_wm = q[10] - q[9];
+      m.tau_w2m = q[10];
       m.lg_wm_a = -2.0 * q[11];
       m.lg_wm_b = 2.0 * q[11] * q[12];
       m.inv_tau_wp = 1.0 / q[13];
       m.inv_tau_fi = 1.0 / q[14];
       m.tau_o1 = q[15];
-      m.tau_o2 = q[16];
+      m.dtau_o = q[16] - q[15];
       m.tau_so1 = q[17];
-      m.dtau_so = q[18] - q[17];
+      m.tau_so2 = q[18];
       m.lg_so_a = -2.0 * q[19];
       m.lg_so_b = 2.0 * q[19] * q[20];
       m.tau_s1 = q[21];
-      m.tau_s2 = q[22];
+      m.dtau_s = q[22] - q[21];
       m.lg_s_a = -2.0 * q[23];
       m.lg_s_b = 2.0 * q[23] * q[24];
       m.inv_tau_si = 1.0 / q[25];

@@ -21,17 +21,17 @@ static hipError_t launch_batch_kernel(bool tangent, int model, int stencil, int 
   return hipErrorInvalidValue;
 }
 
-// Everything except the grid size must agree across the batch.
+// Everything except the grid size and the time step must agree across the batch.
 static int check_uniform(const rd_problem* probs, int32_t n) {
   const rd_problem& q = probs[0];
   for (int32_t i = 1; i < n; ++i) {
     const rd_problem& p = probs[i];
     const bool aniso = q.stencil == RD_LAP9_ANISO;
     if (p.model != q.model || p.scheme != q.scheme || p.stencil != q.stencil || p.bc != q.bc ||
-        p.dx != q.dx || p.dt != q.dt || p.nsteps != q.nsteps || p.D_par != q.D_par ||
+        p.dx != q.dx || p.nsteps != q.nsteps || p.D_par != q.D_par ||
         p.step_k != q.step_k || p.nparams != q.nparams ||
         (aniso && (p.D_perp != q.D_perp || p.theta0 != q.theta0 || p.theta1 != q.theta1)))
-      return fail(RD_EUNSUPPORTED, "problem %d differs from problem 0 in more than its grid size", i);
+      return fail(RD_EUNSUPPORTED, "problem %d differs from problem 0 in more than its grid size and time step", i);
     if (q.nparams > 0 && std::memcmp(p.params, q.params, sizeof(double) * q.nparams) != 0)
       return fail(RD_EUNSUPPORTED, "problem %d has different model parameters from problem 0", i);
   }
@@ -90,6 +90,12 @@ static int run_batched_2d(const rd_problem* probs, int32_t nbatch, double* const
     std::memset(&I, 0, sizeof I);
     I.nx = probs[i].nx;
     I.ny = probs[i].ny;
+    // the time-step constants exactly as derive_constants forms them
+    KConst ci;
+    derive_constants(&probs[i], ci);
+    I.dt = ci.dt;
+    I.h2 = ci.h2;
+    I.h6 = ci.h6;
     for (int f = 0; f < nf; ++f) {
       I.a[f] = f < nv ? fields[i][f] : tangents[i][f - nv];
       I.b[f] = (double*)next;
@@ -215,14 +221,10 @@ extern "C" int rd_step_batched(const rd_problem* probs, int32_t nbatch, double* 
     // 3-D grids: each instance's stage launches in turn (every instance is
     // large enough to fill the GPU on its own), bit-identical to rd_step and
     // rd_jvp on it
-    KConst c;
-    derive_constants(&q, c);
     char* w = (char*)ws;
     for (int32_t i = 0; i < nbatch; ++i) {
-      KConst ci = c;
-      ci.nx = probs[i].nx;
-      ci.ny = probs[i].ny;
-      ci.n_total = (double)probs[i].nx;
+      KConst ci;
+      derive_constants(&probs[i], ci);
       double* a[2 * kMaxFields];
       for (int f = 0; f < nf; ++f) a[f] = f < nv ? fields[i][f] : tangents[i][f - nv];
       rc = run_steps_3d(&probs[i], ci, tangent, a, w, q.nsteps, nullptr, 0, s);

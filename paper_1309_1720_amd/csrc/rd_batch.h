@@ -20,17 +20,19 @@ namespace rd {
 struct BatchInst {
   double* a[kMaxPacked];  // caller's arrays: state fields, then tangent fields
   double* b[kMaxPacked];  // equally sized workspace arrays (ping-pong partner)
+  double dt, h2, h6;      // this instance's time step, dt/2, dt/6
   int nx, ny, nsx, nby, ty;
   int wave_begin;         // first global wave of this instance
 };
 
-constexpr int kInstPerSetup = 24;  // descriptors per setup launch (< 4 KiB of arguments)
+constexpr int kInstPerSetup = 20;  // descriptors per setup launch (< 4 KiB of arguments)
 
 struct BatchSetupArgs {
   BatchInst inst[kInstPerSetup];
   BatchInst* table;
   int first, count;
 };
+static_assert(sizeof(BatchSetupArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 struct BatchArgs {
   const BatchInst* table;
@@ -38,7 +40,7 @@ struct BatchArgs {
   int total_waves;
   int parity;   // 0: a -> b, 1: b -> a
   int nf;       // arrays per instance
-  KConst c;     // shared physics; grid fields are taken from the table
+  KConst c;     // shared physics; grid fields and time steps come from the table
 };
 
 struct BatchCopyArgs {
@@ -49,7 +51,7 @@ struct BatchCopyArgs {
 __global__ void batch_setup_kernel(BatchSetupArgs a);
 __global__ void batch_copy_kernel(BatchCopyArgs a);
 
-template <int MODEL, int STENCIL, int NS, int MODE, int GATE = 0>
+template <int MODEL, int STENCIL, int NS, int MODE, int GATE, int HK>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE>::value)))
 void batch_sweep_kernel(BatchArgs a) {
@@ -72,6 +74,9 @@ void batch_sweep_kernel(BatchArgs a) {
   c.nby = I.nby;
   c.ty = I.ty;
   c.n_total = (double)I.nx;
+  c.dt = I.dt;
+  c.h2 = I.h2;
+  c.h6 = I.h6;
   const double* in[kMaxPacked];
   double* out[kMaxPacked];
 #pragma unroll
@@ -80,47 +85,59 @@ void batch_sweep_kernel(BatchArgs a) {
     out[f] = a.parity ? I.a[f] : I.b[f];
   }
   double* const no_stages[3][kMaxFields] = {};
-  sweep_wave<MODEL, STENCIL, NS, MODE, 1, GATE>(in, out, no_stages, c, wid - I.wave_begin);
+  sweep_wave<MODEL, STENCIL, NS, MODE, 1, GATE, HK>(in, out, no_stages, c, wid - I.wave_begin);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE, int GATE = 0>
+template <int MODEL, int STENCIL, int NS, int MODE, int HK, int GATE = 0>
 hipError_t launch_batch(const BatchArgs& a, hipStream_t stream) {
   if constexpr (GATE != 0 && !ModelTraits<MODEL>::GATED) {
     return hipErrorInvalidValue;
   } else {
     const int blocks = (a.total_waves + 3) / 4;
-    hipLaunchKernelGGL((batch_sweep_kernel<MODEL, STENCIL, NS, MODE, GATE>), dim3(blocks), dim3(256), 0,
+    hipLaunchKernelGGL((batch_sweep_kernel<MODEL, STENCIL, NS, MODE, GATE, HK>), dim3(blocks), dim3(256), 0,
                        stream, a);
     return hipGetLastError();
   }
 }
 
-template <int MODEL, int MODE>
-hipError_t launch_batch_model(int stencil, int scheme, const BatchArgs& a, hipStream_t s) {
+template <int MODEL, int MODE, int HK>
+hipError_t launch_batch_model_hk(int stencil, int scheme, const BatchArgs& a, hipStream_t s) {
   switch (stencil) {
     case RD_LAP5:
-      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP5, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP5, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP5, 4, MODE>(a, s);
-      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP5, 1, MODE, 1>(a, s);
-      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP5, 1, MODE, 2>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP5, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP5, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP5, 4, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP5, 1, MODE, HK, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP5, 1, MODE, HK, 2>(a, s);
       break;
     case RD_LAP9:
-      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9, 4, MODE>(a, s);
-      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP9, 1, MODE, 1>(a, s);
-      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP9, 1, MODE, 2>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9, 4, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP9, 1, MODE, HK, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP9, 1, MODE, HK, 2>(a, s);
       break;
     case RD_LAP9_ANISO:
-      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9_ANISO, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9_ANISO, 4, MODE>(a, s);
-      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE, 1>(a, s);
-      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE, 2>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_batch<MODEL, RD_LAP9_ANISO, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_batch<MODEL, RD_LAP9_ANISO, 4, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE, HK, 1>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_batch<MODEL, RD_LAP9_ANISO, 1, MODE, HK, 2>(a, s);
       break;
   }
   return hipErrorInvalidValue;
+}
+
+// Models with H_k run the smooth or the sharp evaluation of it, chosen by the
+// batch's step_k (the same kernels as rd_step / rd_jvp).
+template <int MODEL, int MODE>
+hipError_t launch_batch_model(int stencil, int scheme, const BatchArgs& a, hipStream_t s) {
+  if constexpr (ModelTraits<MODEL>::GATED) {
+    return a.c.sharp ? launch_batch_model_hk<MODEL, MODE, kHkSharp>(stencil, scheme, a, s)
+                     : launch_batch_model_hk<MODEL, MODE, kHkSmooth>(stencil, scheme, a, s);
+  } else {
+    return launch_batch_model_hk<MODEL, MODE, kHkAny>(stencil, scheme, a, s);
+  }
 }
 
 #define RD_DECLARE_BATCH(model)                                                           \

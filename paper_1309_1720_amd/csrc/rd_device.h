@@ -30,10 +30,12 @@ struct FentonKarmaC {
   double u_c, u_v, inv_tau_d, inv_tau_0, inv_tau_r, inv_tau_si, lg_a, lg_b,
       tau_v2m, dtau_vm, inv_tau_vp, inv_tau_wm, inv_tau_wp;
 };
+// tau_w^- and tau_so blend through logistics and keep both ends; the other
+// tau(u) blend as tau_1 + H (tau_2 - tau_1).
 struct BocfC {
   double u_o, u_u, th_v, th_w, th_vm, th_o, tau_v1m, dtau_vm, inv_tau_vp, tau_w1m,
-      dtau_wm, lg_wm_a, lg_wm_b, inv_tau_wp, inv_tau_fi, tau_o1, tau_o2, tau_so1, dtau_so,
-      lg_so_a, lg_so_b, tau_s1, tau_s2, lg_s_a, lg_s_b, inv_tau_si, inv_tau_winf, w_infstar;
+      tau_w2m, lg_wm_a, lg_wm_b, inv_tau_wp, inv_tau_fi, tau_o1, dtau_o, tau_so1, tau_so2,
+      lg_so_a, lg_so_b, tau_s1, dtau_s, lg_s_a, lg_s_b, inv_tau_si, inv_tau_winf, w_infstar;
 };
 union ModelC {
   BarkleyC bk;
@@ -144,8 +146,8 @@ __device__ __forceinline__ Dual operator/(Dual a, double b) { return Dual(a.v / 
 // steps r <- r + r (1 - d r); within 1 ulp for the positive, finite, normal
 // divisors the reactions use (time constants, 1 + exp(.)).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double exp_lean(double x) {
-  x = fmin(fmax(x, -1.0e4), 1.0e4);  // keeps n in int range; exp saturates far earlier
+// e^x for x in [-1e4, 1e4] (n stays in int range; exp saturates far earlier).
+__device__ __forceinline__ double exp_core(double x) {
   const double n = __builtin_rint(x * 1.4426950408889634);   // log2(e)
   double r = fma(-n, 6.93147180369123816490e-01, x);        // ln2 high part (exact product)
   r = fma(-n, 1.90821492927058770002e-10, r);                // ln2 low part
@@ -163,6 +165,8 @@ __device__ __forceinline__ double exp_lean(double x) {
   p = fma(p, r, 1.0);
   return __builtin_amdgcn_ldexp(p, (int)n);
 }
+
+__device__ __forceinline__ double exp_lean(double x) { return exp_core(fmin(fmax(x, -1.0e4), 1.0e4)); }
 
 __device__ __forceinline__ double recip(double d) {
   double r = __builtin_amdgcn_rcp(d);
@@ -230,37 +234,95 @@ __device__ __forceinline__ Dual step_h(Dual x, const KConst& c) {
   return Dual(h, dh * x.d);
 }
 
+// How a reaction evaluates H_k.  kHkAny: the instructions of step_h, right for
+// a finite k and for the Heaviside limit alike.  kHkSmooth (finite k only):
+// the pairs H(x), H(-x) share one evaluation, since t(-x) = 1 - t(x) and
+// H(1 - t) = 1 - H(t).  kHkSharp (k = inf only): the Heaviside function,
+// H(x) = 1 for x >= 0 (so H(0) = H(-0) = 1, and the pairs do not complement).
+// The fused step kernels pick kHkSmooth or kHkSharp per call; both give the
+// function kHkAny gives, to rounding (kHkSharp exactly).
+enum HkEval { kHkAny = 0, kHkSmooth = 1, kHkSharp = 2 };
+
+// kHkSmooth: t = kx + 1/2 is finite, so its clamp to [0, 1] is written
+// max-then-min, which the compiler folds into the clamp bit of the
+// multiply-add that forms t (no separate min/max instructions).
+__device__ __forceinline__ double step_t_smooth(double x, const KConst& c) {
+  return fmin(fmax(fma(c.k, x, 0.5), 0.0), 1.0);
+}
+template <int HK>
+__device__ __forceinline__ double hk(double x, const KConst& c) {
+  if constexpr (HK == kHkSharp) {
+    return x >= 0.0 ? 1.0 : 0.0;
+  } else if constexpr (HK == kHkSmooth) {
+    const double t = step_t_smooth(x, c);
+    return (t * t) * fma(-2.0, t, 3.0);
+  } else {
+    return step_h(x, c);
+  }
+}
+template <int HK>
+__device__ __forceinline__ Dual hk(Dual x, const KConst& c) {
+  if constexpr (HK == kHkSharp) {
+    return Dual(x.v >= 0.0 ? 1.0 : 0.0, 0.0);
+  } else if constexpr (HK == kHkSmooth) {
+    const double t = step_t_smooth(x.v, c);
+    return Dual((t * t) * fma(-2.0, t, 3.0), (c.k6 * (t * (1.0 - t))) * x.d);
+  } else {
+    return step_h(x, c);
+  }
+}
+// h = H(x), hn = H(-x).  -x is exact, so kHkAny and kHkSharp evaluate
+// H(th - u) exactly as written when x = u - th.
+template <int HK, class T>
+__device__ __forceinline__ void hk_pair(T x, const KConst& c, T& h, T& hn) {
+  h = hk<HK>(x, c);
+  if constexpr (HK == kHkSmooth) hn = 1.0 - h;
+  else hn = hk<HK>(-x, c);
+}
+
 // (1 + tanh(x)) / 2 written as the logistic function 1 / (1 + exp(-2x)): the
 // same function, evaluated with one exp and one division (an FP64 tanh costs
 // several times more), and without the cancellation 1 + tanh(x) suffers for
 // x << 0.  The caller passes the exponent e = -2x, formed from u by one
 // multiply-add with host-computed constants.
 //
-// The exponent is capped at 700 first.  Beyond it the logistic is below
-// 1e-304 (and (1 + tanh x)/2 rounds to exactly 0 in double), but exp(e) would
-// overflow to +inf from e = 709.8 on, and the reciprocal's Newton step turns
-// 1/inf into inf * 0 = NaN.  Capped, the value stays a positive double below
-// 1e-304 and its derivative is 0, as is the derivative of the rounded
+// The exponent is clamped to [-1e4, 600] first (the clamp of exp_lean, with a
+// lower upper end).  Beyond 600 the logistic is below 3e-261 (and
+// (1 + tanh x)/2 rounds to exactly 0 in double), but exp(e) would overflow to
+// +inf from e = 709.8 on, and the reciprocal's Newton step turns 1/inf into
+// inf * 0 = NaN; 600 also leaves tau e^e finite for time constants tau up to
+// 1e47 (logistic_blend_recip).  Clamped, the value stays a positive double
+// below 3e-261 and its derivative is 0, as is the derivative of the rounded
 // (1 + tanh x)/2 there.  Reached only far outside the physiological range
-// (Fenton-Karma u < -34, Bueno-Orovio u < -5.4).
-__device__ __forceinline__ double cap_exponent(double e) { return fmin(e, 700.0); }
-__device__ __forceinline__ Dual cap_exponent(Dual e) {
-  return Dual(fmin(e.v, 700.0), e.v > 700.0 ? 0.0 : e.d);
+// (Fenton-Karma u < -30, Bueno-Orovio u < -4.6).
+constexpr double kExpCap = 600.0;
+__device__ __forceinline__ double exp_capped(double e) { return exp_core(fmax(fmin(e, kExpCap), -1.0e4)); }
+__device__ __forceinline__ Dual exp_capped(Dual e) {
+  const double x = exp_capped(e.v);
+  return Dual(x, e.v > kExpCap ? 0.0 : x * e.d);
 }
 template <class T>
 __device__ __forceinline__ T logistic_of_exponent(T e) {
-  return recip(1.0 + exp(cap_exponent(e)));
+  return recip(1.0 + exp_capped(e));
+}
+// 1 / (tau1 + (tau2 - tau1) L) with L = 1 / (1 + E), E = e^e, the logistic
+// above: equal to (1 + E) / (tau1 E + tau2), one reciprocal instead of two.
+template <class T>
+__device__ __forceinline__ T logistic_blend_recip(T e, double tau1, double tau2) {
+  const T E = exp_capped(e);
+  return (1.0 + E) * recip(mad(E, tau1, tau2));
 }
 
 // ---------------------------------------------------------------------------
 // Reaction rates f = N(y).  Barkley rounds every operation as written (and so
 // matches the oracle bit for bit); the gated models fuse multiply-adds and
-// multiply by reciprocals of their u-dependent time constants.
+// multiply by reciprocals of their u-dependent time constants.  HK selects
+// the evaluation of H_k (HkEval); models without H_k ignore it.
 // ---------------------------------------------------------------------------
 template <int MODEL> struct Reaction;
 
 template <> struct Reaction<RD_MODEL_DIFFUSION> {
-  template <class T>
+  template <class T, int HK = kHkAny>
   __device__ __forceinline__ static void rates(const KConst&, const T*, T* f) {
     f[0] = T(0.0);
   }
@@ -268,7 +330,7 @@ template <> struct Reaction<RD_MODEL_DIFFUSION> {
 
 // Barkley: du = (1/eps) u (1 - u)(u - (v + b)/a), dv = u - v.
 template <> struct Reaction<RD_MODEL_BARKLEY> {
-  template <class T>
+  template <class T, int HK = kHkAny>
   __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const BarkleyC& m = c.m.bk;
     const T u = y[0], v = y[1];
@@ -282,7 +344,7 @@ template <> struct Reaction<RD_MODEL_BARKLEY> {
 // du = u - v - u^3, dv = eps (u - a1 v - a0).  Rounded as written (matches the
 // oracle bit for bit).
 template <> struct Reaction<RD_MODEL_FHN> {
-  template <class T>
+  template <class T, int HK = kHkAny>
   __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const FhnC& m = c.m.fh;
     const T u = y[0], v = y[1];
@@ -296,12 +358,12 @@ template <> struct Reaction<RD_MODEL_FHN> {
 // J_si = -w (1 + tanh(k_si (u - u_csi))) / (2 tau_si),
 // dv = (1-p)(1-v)/tau_v^-(u) - p v/tau_v^+, dw = (1-p)(1-w)/tau_w^- - p w/tau_w^+.
 template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
-  template <class T>
+  template <class T, int HK = kHkAny>
   __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const FentonKarmaC& m = c.m.fk;
     const T u = y[0], v = y[1], w = y[2];
-    const T p = step_h(u - m.u_c, c);
-    const T q = step_h(u - m.u_v, c);
+    const T p = hk<HK>(u - m.u_c, c);
+    const T q = hk<HK>(u - m.u_v, c);
     const T one_p = 1.0 - p;
     const T j_fi = -(((v * p) * (1.0 - u)) * (u - m.u_c)) * m.inv_tau_d;
     const T j_so = mad(u * one_p, m.inv_tau_0, p * m.inv_tau_r);
@@ -313,12 +375,12 @@ template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
   }
   // dv = alpha_v v + beta_v, dw = alpha_w w + beta_w (the same rates, sorted
   // by powers of the gate).
-  template <class T>
+  template <class T, int HK = kHkAny>
   __device__ __forceinline__ static void gates(const KConst& c, const T* y, T* al, T* be) {
     const FentonKarmaC& m = c.m.fk;
     const T u = y[0];
-    const T p = step_h(u - m.u_c, c);
-    const T q = step_h(u - m.u_v, c);
+    const T p = hk<HK>(u - m.u_c, c);
+    const T q = hk<HK>(u - m.u_v, c);
     const T one_p = 1.0 - p;
     const T r_vm = recip(mad(q, m.dtau_vm, T(m.tau_v2m)));
     al[1] = -(one_p * r_vm) - p * m.inv_tau_vp;
@@ -330,60 +392,65 @@ template <> struct Reaction<RD_MODEL_FENTON_KARMA> {
 
 // Bueno-Orovio four-variable model, Eq. (5) with the currents and the
 // alpha/beta gate form; tau(u), v_inf, w_inf as in Bueno-Orovio et al. (2008).
+// The u-dependent quantities both the rates and the gate coefficients use.
+template <class T>
+struct BocfTerms {
+  T h_v, h_v_neg, h_w, h_w_neg, h_o, v_inf;
+  T r_vm, r_wm, r_s;  // 1/tau_v^-, 1/tau_w^-, 1/tau_s
+  T w_inf, s_inf;
+};
 template <> struct Reaction<RD_MODEL_BOCF> {
-  // dv, dw as alpha g + beta (as the rates below form them); ds = (s_inf - s)/tau_s
-  // gives alpha_s = -1/tau_s, beta_s = s_inf/tau_s.
-  template <class T>
-  __device__ __forceinline__ static void gates(const KConst& c, const T* y, T* al, T* be) {
+  template <class T, int HK>
+  __device__ __forceinline__ static BocfTerms<T> terms(const KConst& c, const T& u) {
     const BocfC& m = c.m.bo;
-    const T u = y[0];
-    const T h_v = step_h(u - m.th_v, c);
-    const T h_v_neg = step_h(m.th_v - u, c);
-    const T h_w = step_h(u - m.th_w, c);
-    const T h_w_neg = step_h(m.th_w - u, c);
-    const T h_vm = step_h(u - m.th_vm, c);
-    const T h_o = step_h(u - m.th_o, c);
-    const T r_vm = recip(mad(h_vm, m.dtau_vm, T(m.tau_v1m)));
-    const T r_wm = recip(mad(m.dtau_wm, logistic_of_exponent(mad(u, m.lg_wm_a, m.lg_wm_b)), T(m.tau_w1m)));
-    const T r_s = recip(mad(1.0 - h_w, m.tau_s1, h_w * m.tau_s2));
-    const T v_inf = step_h(m.th_vm - u, c);
-    const T w_inf = mad(1.0 - h_o, mad(-u, m.inv_tau_winf, 1.0), h_o * m.w_infstar);
-    al[1] = mad(-h_v, m.inv_tau_vp, -(h_v_neg * r_vm));
-    be[1] = (h_v_neg * v_inf) * r_vm;
-    al[2] = mad(-h_w, m.inv_tau_wp, -(h_w_neg * r_wm));
-    be[2] = (h_w_neg * w_inf) * r_wm;
-    al[3] = -r_s;
-    be[3] = logistic_of_exponent(mad(u, m.lg_s_a, m.lg_s_b)) * r_s;
+    BocfTerms<T> t;
+    hk_pair<HK>(u - m.th_v, c, t.h_v, t.h_v_neg);
+    hk_pair<HK>(u - m.th_w, c, t.h_w, t.h_w_neg);
+    T h_vm;
+    hk_pair<HK>(u - m.th_vm, c, h_vm, t.v_inf);  // v_inf = H(th_v^- - u)
+    t.h_o = hk<HK>(u - m.th_o, c);
+    t.r_vm = recip(mad(h_vm, m.dtau_vm, T(m.tau_v1m)));                 // tau_v1^- + H (tau_v2^- - tau_v1^-)
+    t.r_wm = logistic_blend_recip(mad(u, m.lg_wm_a, m.lg_wm_b), m.tau_w1m, m.tau_w2m);
+    t.r_s = recip(mad(t.h_w, m.dtau_s, T(m.tau_s1)));                  // tau_s1 + H (tau_s2 - tau_s1)
+    // w_inf = (1 - H_o)(1 - u / tau_winf) + H_o w_inf*
+    const T a = mad(-u, m.inv_tau_winf, 1.0);
+    t.w_inf = mad(t.h_o, m.w_infstar - a, a);
+    t.s_inf = logistic_of_exponent(mad(u, m.lg_s_a, m.lg_s_b));
+    return t;
   }
 
-  template <class T>
+  // dv, dw as alpha g + beta (as the rates below form them); ds = (s_inf - s)/tau_s
+  // gives alpha_s = -1/tau_s, beta_s = s_inf/tau_s.
+  template <class T, int HK = kHkAny>
+  __device__ __forceinline__ static void gates(const KConst& c, const T* y, T* al, T* be) {
+    const BocfC& m = c.m.bo;
+    const BocfTerms<T> t = terms<T, HK>(c, y[0]);
+    al[1] = mad(-t.h_v, m.inv_tau_vp, -(t.h_v_neg * t.r_vm));
+    be[1] = (t.h_v_neg * t.v_inf) * t.r_vm;
+    al[2] = mad(-t.h_w, m.inv_tau_wp, -(t.h_w_neg * t.r_wm));
+    be[2] = (t.h_w_neg * t.w_inf) * t.r_wm;
+    al[3] = -t.r_s;
+    be[3] = t.s_inf * t.r_s;
+  }
+
+  template <class T, int HK = kHkAny>
   __device__ __forceinline__ static void rates(const KConst& c, const T* y, T* f) {
     const BocfC& m = c.m.bo;
     const T u = y[0], v = y[1], w = y[2], s = y[3];
-    const T h_v = step_h(u - m.th_v, c);
-    const T h_v_neg = step_h(m.th_v - u, c);
-    const T h_w = step_h(u - m.th_w, c);
-    const T h_w_neg = step_h(m.th_w - u, c);
-    const T h_vm = step_h(u - m.th_vm, c);
-    const T h_o = step_h(u - m.th_o, c);
-    const T r_vm = recip(mad(h_vm, m.dtau_vm, T(m.tau_v1m)));           // 1/tau_v^-
-    const T r_wm = recip(mad(m.dtau_wm, logistic_of_exponent(mad(u, m.lg_wm_a, m.lg_wm_b)), T(m.tau_w1m)));
-    const T r_so = recip(mad(m.dtau_so, logistic_of_exponent(mad(u, m.lg_so_a, m.lg_so_b)), T(m.tau_so1)));
-    const T r_s = recip(mad(1.0 - h_w, m.tau_s1, h_w * m.tau_s2));                 // 1/tau_s
-    const T r_o = recip(mad(1.0 - h_o, m.tau_o1, h_o * m.tau_o2));                 // 1/tau_o
-    const T v_inf = step_h(m.th_vm - u, c);
-    const T w_inf = mad(1.0 - h_o, mad(-u, m.inv_tau_winf, 1.0), h_o * m.w_infstar);
-    const T j_fi = -(((v * h_v) * (u - m.th_v)) * (m.u_u - u)) * m.inv_tau_fi;
-    const T j_so = mad((u - m.u_o) * h_w_neg, r_o, h_w * r_so);
-    const T j_si = -((h_w * w) * s) * m.inv_tau_si;
+    const BocfTerms<T> t = terms<T, HK>(c, u);
+    const T r_so = logistic_blend_recip(mad(u, m.lg_so_a, m.lg_so_b), m.tau_so1, m.tau_so2);  // 1/tau_so
+    const T r_o = recip(mad(t.h_o, m.dtau_o, T(m.tau_o1)));                                   // 1/tau_o
+    const T j_fi = -(((v * t.h_v) * (u - m.th_v)) * (m.u_u - u)) * m.inv_tau_fi;
+    const T j_so = mad((u - m.u_o) * t.h_w_neg, r_o, t.h_w * r_so);
+    const T j_si = -((t.h_w * w) * s) * m.inv_tau_si;
     f[0] = -((j_fi + j_so) + j_si);
-    const T alpha_v = mad(-h_v, m.inv_tau_vp, -(h_v_neg * r_vm));
-    const T beta_v = (h_v_neg * v_inf) * r_vm;
+    const T alpha_v = mad(-t.h_v, m.inv_tau_vp, -(t.h_v_neg * t.r_vm));
+    const T beta_v = (t.h_v_neg * t.v_inf) * t.r_vm;
     f[1] = mad(alpha_v, v, beta_v);
-    const T alpha_w = mad(-h_w, m.inv_tau_wp, -(h_w_neg * r_wm));
-    const T beta_w = (h_w_neg * w_inf) * r_wm;
+    const T alpha_w = mad(-t.h_w, m.inv_tau_wp, -(t.h_w_neg * t.r_wm));
+    const T beta_w = (t.h_w_neg * t.w_inf) * t.r_wm;
     f[2] = mad(alpha_w, w, beta_w);
-    f[3] = (logistic_of_exponent(mad(u, m.lg_s_a, m.lg_s_b)) - s) * r_s;
+    f[3] = (t.s_inf - s) * t.r_s;
   }
 };
 
@@ -403,7 +470,7 @@ __device__ __forceinline__ T gate_step(T g, T al, T be, double dt) {
 // The step of a gate scheme on a packed row y (state, then tangent when TAN):
 // explicit Euler for the diffusive field with its full rate k (diffusion +
 // reaction), gate_step for the gates.  zn receives the new packed row.
-template <int MODEL, bool TAN, int GATE>
+template <int MODEL, bool TAN, int GATE, int HK = kHkAny>
 __device__ __forceinline__ void gate_scheme_step(const KConst& c, const double* y, const double* k,
                                                  double* zn) {
   constexpr int NV = ModelTraits<MODEL>::NV;
@@ -411,7 +478,7 @@ __device__ __forceinline__ void gate_scheme_step(const KConst& c, const double* 
   zn[0] = y[0] + c.dt * k[0];
   if constexpr (!TAN) {
     double al[NV], be[NV];
-    Reaction<MODEL>::template gates<double>(c, y, al, be);
+    Reaction<MODEL>::template gates<double, HK>(c, y, al, be);
 #pragma unroll
     for (int g = 1; g < NV; ++g) zn[g] = gate_step<GATE>(y[g], al[g], be[g], c.dt);
   } else {
@@ -419,7 +486,7 @@ __device__ __forceinline__ void gate_scheme_step(const KConst& c, const double* 
     Dual yd[NV], al[NV], be[NV];
 #pragma unroll
     for (int f = 0; f < NV; ++f) yd[f] = Dual(y[f], y[NV + f]);
-    Reaction<MODEL>::template gates<Dual>(c, yd, al, be);
+    Reaction<MODEL>::template gates<Dual, HK>(c, yd, al, be);
 #pragma unroll
     for (int g = 1; g < NV; ++g) {
       const Dual r = gate_step<GATE>(yd[g], al[g], be[g], c.dt);
@@ -431,16 +498,16 @@ __device__ __forceinline__ void gate_scheme_step(const KConst& c, const double* 
 
 // N(y) (TAN = false) or N(y) and J_N(y) dy (TAN = true) for a packed row
 // y[0..NV) = state, y[NV..2NV) = tangent; results packed the same way.
-template <int MODEL, bool TAN>
+template <int MODEL, bool TAN, int HK = kHkAny>
 __device__ __forceinline__ void eval_rates(const KConst& c, const double* y, double* k) {
   constexpr int NV = ModelTraits<MODEL>::NV;
   if constexpr (!TAN) {
-    Reaction<MODEL>::template rates<double>(c, y, k);
+    Reaction<MODEL>::template rates<double, HK>(c, y, k);
   } else {
     Dual yd[NV], kd[NV];
 #pragma unroll
     for (int f = 0; f < NV; ++f) yd[f] = Dual(y[f], y[NV + f]);
-    Reaction<MODEL>::template rates<Dual>(c, yd, kd);
+    Reaction<MODEL>::template rates<Dual, HK>(c, yd, kd);
 #pragma unroll
     for (int f = 0; f < NV; ++f) {
       k[f] = kd[f].v;

@@ -46,7 +46,7 @@ template <int MODEL, int NS, int MODE> struct PipeShape {
   static constexpr int total = U_doubles + G_doubles + A_doubles;
 };
 
-template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE>
+template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int HK>
 __device__ __forceinline__ void pipe_block_impl(const double* const* in, double* const* out,
                                                 double* const (*ys)[kMaxFields], const KConst& c,
                                                 int blk, double* lds) {
@@ -148,7 +148,7 @@ __device__ __forceinline__ void pipe_block_impl(const double* const* in, double*
         lap[d] = diffusion_rows<STENCIL, EDGE>(urow(s, ru, d), urow(s, rho, d), urow(s, rd, d), il, iw, ie,
                                                col, rho, c, c.dcoef[d % NDF]);
       double k[NF];
-      eval_rates<MODEL, TAN>(c, y, k);
+      eval_rates<MODEL, TAN, HK>(c, y, k);
 #pragma unroll
       for (int d = 0; d < ND; ++d) k[comp(d)] = lap[d] + k[comp(d)];
 
@@ -205,51 +205,63 @@ __device__ __forceinline__ void pipe_block_impl(const double* const* in, double*
   }
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int HK>
 __device__ __forceinline__ void pipe_block(const double* const* in, double* const* out,
                                            double* const (*ys)[kMaxFields], const KConst& c, int blk,
                                            double* lds) {
   const int x0 = (blk / c.nby) * (kWave - 2 * NS) - NS;
   if (strip_touches_edge(x0, c))
-    pipe_block_impl<MODEL, STENCIL, NS, MODE, true>(in, out, ys, c, blk, lds);
+    pipe_block_impl<MODEL, STENCIL, NS, MODE, true, HK>(in, out, ys, c, blk, lds);
   else
-    pipe_block_impl<MODEL, STENCIL, NS, MODE, false>(in, out, ys, c, blk, lds);
+    pipe_block_impl<MODEL, STENCIL, NS, MODE, false, HK>(in, out, ys, c, blk, lds);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int HK>
 __global__ __launch_bounds__(kWave * NS) void pipe_kernel(SweepArgs a) {
   __shared__ double lds[PipeShape<MODEL, NS, MODE>::total];
-  pipe_block<MODEL, STENCIL, NS, MODE>(a.in, a.out, a.ys, a.c, xcd_order((int)blockIdx.x, (int)gridDim.x), lds);
+  pipe_block<MODEL, STENCIL, NS, MODE, HK>(a.in, a.out, a.ys, a.c, xcd_order((int)blockIdx.x, (int)gridDim.x), lds);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int HK>
 hipError_t launch_pipe(const SweepArgs& a, hipStream_t stream) {
   if (MODE == kModeStages && NS == 1) return hipSuccess;  // Euler has no inner stage
-  hipLaunchKernelGGL((pipe_kernel<MODEL, STENCIL, NS, MODE>), dim3(a.c.nsx * a.c.nby), dim3(kWave * NS),
+  hipLaunchKernelGGL((pipe_kernel<MODEL, STENCIL, NS, MODE, HK>), dim3(a.c.nsx * a.c.nby), dim3(kWave * NS),
                      0, stream, a);
   return hipGetLastError();
 }
 
-template <int MODEL, int MODE>
-hipError_t launch_pipe_model(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
+template <int MODEL, int MODE, int HK>
+hipError_t launch_pipe_model_hk(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
   switch (stencil) {
     case RD_LAP5:
-      if (scheme == RD_SCHEME_EULER) return launch_pipe<MODEL, RD_LAP5, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_pipe<MODEL, RD_LAP5, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_pipe<MODEL, RD_LAP5, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_pipe<MODEL, RD_LAP5, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_pipe<MODEL, RD_LAP5, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_pipe<MODEL, RD_LAP5, 4, MODE, HK>(a, s);
       break;
     case RD_LAP9:
-      if (scheme == RD_SCHEME_EULER) return launch_pipe<MODEL, RD_LAP9, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_pipe<MODEL, RD_LAP9, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_pipe<MODEL, RD_LAP9, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_pipe<MODEL, RD_LAP9, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_pipe<MODEL, RD_LAP9, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_pipe<MODEL, RD_LAP9, 4, MODE, HK>(a, s);
       break;
     case RD_LAP9_ANISO:
-      if (scheme == RD_SCHEME_EULER) return launch_pipe<MODEL, RD_LAP9_ANISO, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_pipe<MODEL, RD_LAP9_ANISO, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_pipe<MODEL, RD_LAP9_ANISO, 4, MODE>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_pipe<MODEL, RD_LAP9_ANISO, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_pipe<MODEL, RD_LAP9_ANISO, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_pipe<MODEL, RD_LAP9_ANISO, 4, MODE, HK>(a, s);
       break;
   }
   return hipErrorInvalidValue;
+}
+
+// Models with H_k run the smooth or the sharp evaluation of it (as the sweep
+// kernels do, so that both variants give the same bits).
+template <int MODEL, int MODE>
+hipError_t launch_pipe_model(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
+  if constexpr (ModelTraits<MODEL>::GATED) {
+    return a.c.sharp ? launch_pipe_model_hk<MODEL, MODE, kHkSharp>(stencil, scheme, a, s)
+                     : launch_pipe_model_hk<MODEL, MODE, kHkSmooth>(stencil, scheme, a, s);
+  } else {
+    return launch_pipe_model_hk<MODEL, MODE, kHkAny>(stencil, scheme, a, s);
+  }
 }
 
 }  // namespace rd

@@ -108,7 +108,7 @@ template <int MODEL, int NS, int MODE> struct SweepPrefetch {
 // of z_{n+k} (the row copy k - 1 finished in the same iteration; copy 0 the
 // row just loaded) and runs its stage s on row r - k NS - s, so the launch
 // needs KS = K NS halo columns and ramp rows.
-template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1, int GATE = 0>
+template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1, int GATE = 0, int HK = kHkAny>
 __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double* const* out,
                                                 double* const (*ys)[kMaxFields], const KConst& c,
                                                 int wid) {
@@ -289,7 +289,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         for (int d = 0; d < ND; ++d)
           lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c, c.dcoef[d % NDF]);
         double kr[NF];
-        eval_rates<MODEL, TAN>(c, y, kr);
+        eval_rates<MODEL, TAN, HK>(c, y, kr);
 #pragma unroll
         for (int d = 0; d < ND; ++d) kr[comp(d)] = lap[d] + kr[comp(d)];
 
@@ -303,7 +303,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 #pragma unroll
             for (int f = 0; f < NF; ++f) zn[f] = zr[k][1][f] + c.dt * kr[f];
           } else {
-            gate_scheme_step<MODEL, TAN, GATE>(c, zr[k][1], kr, zn);
+            gate_scheme_step<MODEL, TAN, GATE, HK>(c, zr[k][1], kr, zn);
           }
           if (!last) {
 #pragma unroll
@@ -373,84 +373,97 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 }
 
 // Strips that touch the grid's x-edges apply the mirror; interior strips skip it.
-template <int MODEL, int STENCIL, int NS, int MODE, int K = 1, int GATE = 0>
+template <int MODEL, int STENCIL, int NS, int MODE, int K = 1, int GATE = 0, int HK = kHkAny>
 __device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
                                            double* const (*ys)[kMaxFields], const KConst& c,
                                            int wid) {
   const int x0 = (wid / c.nby) * (kWave - 2 * K * NS) - K * NS;
   if (strip_touches_edge(x0, c))
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK>(in, out, ys, c, wid);
   else
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK>(in, out, ys, c, wid);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE>
+template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE, int HK>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(SweepOccupancy<MODEL, STENCIL, NS, MODE, K>::value)))
 void sweep_kernel(SweepArgs a) {
   const int blk = xcd_order((int)blockIdx.x, (int)gridDim.x);
   const int wid = __builtin_amdgcn_readfirstlane(blk * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave));
   if (wid >= a.c.nsx * a.c.nby) return;  // whole waves only: no barrier follows
-  sweep_wave<MODEL, STENCIL, NS, MODE, K, GATE>(a.in, a.out, a.ys, a.c, wid);
+  sweep_wave<MODEL, STENCIL, NS, MODE, K, GATE, HK>(a.in, a.out, a.ys, a.c, wid);
 }
 
-template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE = 0>
+template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE, int HK>
 hipError_t launch_sweep_k(const SweepArgs& a, hipStream_t stream) {
   const int waves = a.c.nsx * a.c.nby;
   const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE, K, GATE>), dim3(blocks), dim3(256), 0, stream, a);
+  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE, K, GATE, HK>), dim3(blocks), dim3(256), 0, stream,
+                     a);
   return hipGetLastError();
 }
 
 // One step of a gate scheme (gated models, state or state and tangent).
-template <int MODEL, int STENCIL, int MODE, int GATE>
+template <int MODEL, int STENCIL, int MODE, int GATE, int HK>
 hipError_t launch_sweep_gate(const SweepArgs& a, hipStream_t stream) {
   if constexpr (ModelTraits<MODEL>::GATED && MODE != kModeStages)
-    return launch_sweep_k<MODEL, STENCIL, 1, MODE, 1, GATE>(a, stream);
+    return launch_sweep_k<MODEL, STENCIL, 1, MODE, 1, GATE, HK>(a, stream);
   return hipErrorInvalidValue;
 }
 
 // One launch of a.c.ksteps steps (1 unless MultiStep allows more).
-template <int MODEL, int STENCIL, int NS, int MODE>
+template <int MODEL, int STENCIL, int NS, int MODE, int HK>
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t stream) {
   if (MODE == kModeStages && NS == 1) return hipSuccess;  // Euler has no inner stage
   constexpr int KMAX = MultiStep<MODEL, NS, MODE>::max;
   switch (a.c.ksteps) {
-    case 1: return launch_sweep_k<MODEL, STENCIL, NS, MODE, 1>(a, stream);
-    case 2: if constexpr (KMAX >= 2) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 2>(a, stream); break;
-    case 4: if constexpr (KMAX >= 4) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 4>(a, stream); break;
-    case 8: if constexpr (KMAX >= 8) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 8>(a, stream); break;
+    case 1: return launch_sweep_k<MODEL, STENCIL, NS, MODE, 1, 0, HK>(a, stream);
+    case 2: if constexpr (KMAX >= 2) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 2, 0, HK>(a, stream); break;
+    case 4: if constexpr (KMAX >= 4) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 4, 0, HK>(a, stream); break;
+    case 8: if constexpr (KMAX >= 8) return launch_sweep_k<MODEL, STENCIL, NS, MODE, 8, 0, HK>(a, stream); break;
   }
   return hipErrorInvalidValue;
 }
 
-// Dispatch over stencil and scheme for one model and mode.
-template <int MODEL, int MODE>
-hipError_t launch_sweep_model(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
+// Dispatch over stencil and scheme for one model, mode and H_k evaluation.
+template <int MODEL, int MODE, int HK>
+hipError_t launch_sweep_model_hk(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
   switch (stencil) {
     case RD_LAP5:
-      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP5, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP5, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP5, 4, MODE>(a, s);
-      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP5, MODE, 1>(a, s);
-      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP5, MODE, 2>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP5, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP5, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP5, 4, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP5, MODE, 1, HK>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP5, MODE, 2, HK>(a, s);
       break;
     case RD_LAP9:
-      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9, 4, MODE>(a, s);
-      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP9, MODE, 1>(a, s);
-      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP9, MODE, 2>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9, 4, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP9, MODE, 1, HK>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP9, MODE, 2, HK>(a, s);
       break;
     case RD_LAP9_ANISO:
-      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9_ANISO, 1, MODE>(a, s);
-      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9_ANISO, 2, MODE>(a, s);
-      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9_ANISO, 4, MODE>(a, s);
-      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP9_ANISO, MODE, 1>(a, s);
-      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP9_ANISO, MODE, 2>(a, s);
+      if (scheme == RD_SCHEME_EULER) return launch_sweep<MODEL, RD_LAP9_ANISO, 1, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_HEUN) return launch_sweep<MODEL, RD_LAP9_ANISO, 2, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RK4) return launch_sweep<MODEL, RD_LAP9_ANISO, 4, MODE, HK>(a, s);
+      if (scheme == RD_SCHEME_RUSH_LARSEN) return launch_sweep_gate<MODEL, RD_LAP9_ANISO, MODE, 1, HK>(a, s);
+      if (scheme == RD_SCHEME_IMPLICIT_EULER) return launch_sweep_gate<MODEL, RD_LAP9_ANISO, MODE, 2, HK>(a, s);
       break;
   }
   return hipErrorInvalidValue;
+}
+
+// Models with H_k run the smooth or the sharp evaluation of it (HkEval),
+// chosen by the call's step_k; the others have one set of kernels.
+template <int MODEL, int MODE>
+hipError_t launch_sweep_model(int stencil, int scheme, const SweepArgs& a, hipStream_t s) {
+  if constexpr (ModelTraits<MODEL>::GATED) {
+    return a.c.sharp ? launch_sweep_model_hk<MODEL, MODE, kHkSharp>(stencil, scheme, a, s)
+                     : launch_sweep_model_hk<MODEL, MODE, kHkSmooth>(stencil, scheme, a, s);
+  } else {
+    return launch_sweep_model_hk<MODEL, MODE, kHkAny>(stencil, scheme, a, s);
+  }
 }
 
 // Columns each wave produces for a scheme of `ns` stages.

@@ -9,7 +9,7 @@ nsteps-step flow of problem i.  Each Newton step solves (dPhi_i - I) dz_i =
 -G_i with restarted GMRES; the GMRES iterations of all members advance in
 lockstep, so each Krylov iteration is one batched launch sequence
 (rd_step_batched with tangents) per group of members that share their
-physics (everything but the grid size).  The
+physics (everything but the grid size and the time step).  The
 Jacobian-vector products are exact (tangent-linear kernels), or central
 finite differences of two forward runs for comparison.  Vector algebra runs
 in the library's kernels (rd_vec_gram, rd_vec_lincomb); the small Hessenberg
@@ -34,7 +34,9 @@ def _flat(fields) -> torch.Tensor:
 
 
 def _physics(p: B.Problem):
-    return (p.model, p.scheme, p.stencil, p.dx, p.dt, p.nsteps, p.D_par, p.D_perp, p.theta0, p.theta1,
+    """What members of one rd_step_batched call must share (all but the grid
+    size and the time step)."""
+    return (p.model, p.scheme, p.stencil, p.dx, p.nsteps, p.D_par, p.D_perp, p.theta0, p.theta1,
             p.step_k, tuple(p.params), p.bc)
 
 
@@ -176,3 +178,109 @@ def newton_krylov(probs, states, tol: float = 1e-12, max_newton: int = 10, jvp: 
         for zi, dz in zip(z, sol.x):
             B.vec_lincomb(zi, 1.0, [dz], [1.0])
     return NewtonResult([_views(zi, p) for zi, p in zip(z, probs)], residuals, kits)
+
+
+@dataclass
+class PeriodicOrbitResult:
+    states: list             # converged states (lists of field tensors)
+    periods: list            # converged periods T_i
+    residuals: list          # per Newton iteration: max_i ||Phi(z_i; T_i) - z_i|| / ||z_i||
+    krylov_iterations: list  # per Newton iteration: GMRES iterations per member
+    periods_history: list    # per Newton iteration: the periods it started from
+
+
+def _with_period(prob: B.Problem, period: float) -> B.Problem:
+    """The member's flow over time ``period``: its nsteps steps of dt = period / nsteps."""
+    from dataclasses import replace
+    return replace(prob, dt=float(period) / prob.nsteps, checkpoint_every=0)
+
+
+def periodic_orbit(probs, states, periods, tol: float = 1e-10, max_newton: int = 16, jvp: str = "exact",
+                   fd_eps: float = 1e-7, period_eps: float = 1e-6, restart: int = 60,
+                   max_cycles: int = 4) -> PeriodicOrbitResult:
+    """Periodic orbits of the discretised flow with unknown periods: states
+    z_i and periods T_i with Phi(z_i; T_i) = z_i, where Phi(z; T) is member
+    i's nsteps-step flow at the step dt = T / nsteps (nsteps fixed, so the
+    period varies continuously).
+
+    A periodic orbit is a one-parameter family (every point of the loop is a
+    solution), so the flow direction is a null vector of dPhi - I.  Each
+    Newton step solves the bordered system
+
+        [ dPhi/dz - I   c ] [dz]   [-G]          G = Phi(z; T) - z,
+        [ c^T           0 ] [dT] = [ 0],         c = dPhi/dT,
+
+    whose last row is the phase condition: the correction is orthogonal to
+    c, the flow direction at the orbit's end point (at convergence the flow
+    direction at z itself), which removes the shift along the loop.  c is a
+    central difference in T (two extra forward runs per Newton step); the
+    products dPhi/dz v are the exact tangent-linear ones (jvp="exact": one
+    batched state+tangent run per Krylov iteration, all members in lockstep)
+    or central differences of two forward runs (jvp="fd", step fd_eps
+    relative to ||z||), for comparison.  Bordered vectors are flat tensors
+    of the member's state followed by one entry for T.
+    """
+    if jvp not in ("exact", "fd"):
+        raise ValueError("jvp must be 'exact' or 'fd'")
+    K = len(probs)
+    if len(states) != K or len(periods) != K:
+        raise ValueError("one state and one period per problem")
+    z = [_flat(s).clone() for s in states]
+    T = [float(t) for t in periods]
+    n = [zi.numel() for zi in z]
+
+    def flow(members, flats, period_of):
+        fields = [_views(f.clone(), probs[i]) for i, f in zip(members, flats)]
+        _batched([_with_period(probs[i], period_of(i)) for i in range(K)], members, fields)
+        return [_flat(f) for f in fields]
+
+    residuals, kits, thist = [], [], []
+    for _ in range(max_newton + 1):
+        members = list(range(K))
+        phi = flow(members, z, lambda i: T[i])
+        g = [B.vec_lincomb(p, 1.0, [zi], [-1.0]) for p, zi in zip(phi, z)]
+        rel = [_norm(gi) / max(_norm(zi), 1.0) for gi, zi in zip(g, z)]
+        residuals.append(max(rel))
+        thist.append(list(T))
+        if max(rel) <= tol or len(kits) == max_newton:
+            break
+        # c = dPhi/dT by a central difference in T
+        hp = [T[i] * (1.0 + period_eps) for i in members]
+        hm = [T[i] * (1.0 - period_eps) for i in members]
+        plus = flow(members, z, lambda i: hp[i])
+        minus = flow(members, z, lambda i: hm[i])
+        cvec = [B.vec_lincomb(p, 1.0 / (hp[i] - hm[i]), [m], [-1.0 / (hp[i] - hm[i])])
+                for i, (p, m) in enumerate(zip(plus, minus))]
+        zprobs = [_with_period(probs[i], T[i]) for i in members]
+
+        def matvec_many(pairs):
+            idx = [i for i, _ in pairs]
+            vz = [v[: n[i]] for i, v in pairs]
+            if jvp == "exact":
+                fields = [_views(z[i].clone(), probs[i]) for i in idx]
+                tans = [_views(v.clone(), probs[i]) for i, v in zip(idx, vz)]
+                _batched(zprobs, idx, fields, tans)
+                jv = [_flat(t) for t in tans]
+            else:
+                eps = [fd_eps * max(_norm(z[i]), 1.0) / max(_norm(v), 1e-300) for i, v in zip(idx, vz)]
+                fp = flow(idx, [B.vec_lincomb(z[i].clone(), 1.0, [v], [e]) for i, v, e in zip(idx, vz, eps)],
+                          lambda i: T[i])
+                fm = flow(idx, [B.vec_lincomb(z[i].clone(), 1.0, [v], [-e]) for i, v, e in zip(idx, vz, eps)],
+                          lambda i: T[i])
+                jv = [B.vec_lincomb(p, 0.5 / e, [m], [-0.5 / e]) for p, m, e in zip(fp, fm, eps)]
+            out = []
+            for (m, v), j, vzi in zip(pairs, jv, vz):
+                vt = float(v[n[m]].item())
+                B.vec_lincomb(j, 1.0, [vzi, cvec[m]], [-1.0, vt])   # (dPhi - I) vz + c vT
+                out.append(torch.cat([j, B.vec_gram([cvec[m]], vzi)]))  # phase row <c, vz>
+            return out
+
+        forcing = [min(1e-2, max(r, 1e-14) ** 0.5) for r in rel]
+        rhs = [torch.cat([B.vec_lincomb(gi.clone(), -1.0), torch.zeros(1, dtype=gi.dtype, device=gi.device)])
+               for gi in g]
+        sol = gmres_lockstep(matvec_many, rhs, forcing, restart, max_cycles)
+        kits.append(sol.iterations)
+        for i, dx in enumerate(sol.x):
+            B.vec_lincomb(z[i], 1.0, [dx[: n[i]].contiguous()], [1.0])
+            T[i] += float(dx[n[i]].item())
+    return PeriodicOrbitResult([_views(zi, p) for zi, p in zip(z, probs)], T, residuals, kits, thist)

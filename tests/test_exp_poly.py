@@ -20,10 +20,12 @@ NUM = r"([-+]?[0-9.]+(?:e[-+]?[0-9]+)?)"
 
 
 def exp_lean_source() -> str:
+    """exp_lean (the clamp) followed by exp_core (the rest)."""
     with open(os.path.join(CSRC, "rd_device.h")) as fh:
         src = fh.read()
-    start = src.index("__device__ __forceinline__ double exp_lean(double x)")
-    return src[start:src.index("\n}\n", start)]
+    lean = src.index("__device__ __forceinline__ double exp_lean(double x)")
+    core = src.index("__device__ __forceinline__ double exp_core(double x)")
+    return src[lean:src.index("\n", lean)] + "\n" + src[core:src.index("\n}\n", core)]
 
 
 def constants():

@@ -1,5 +1,7 @@
 """rd_step_batched: many problems on uneven grids in one launch per step must
 equal per-problem rd_step / rd_jvp bit for bit (and hence the oracle)."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -61,12 +63,43 @@ def test_batched_tangent_matches_oracle():
         assert rel_linf(host(tans[k]), jr) <= 1e-11
 
 
-def test_batched_rejects_mixed_physics():
+@pytest.mark.parametrize("field,value", [("dx", 0.03), ("nsteps", 3), ("step_k", 20.0)])
+def test_batched_rejects_mixed_physics(field, value):
     cases = batch_setup("fk", "lap9", "rk4", 2, sizes=[(16, 16), (20, 20)])
     probs = [pr for _, pr, _, _ in cases]
-    probs[1].dt = 0.05
+    setattr(probs[1], field, value)
     with pytest.raises(rd.RDError, match="RD_EUNSUPPORTED"):
         rd.step_batched(probs, [dev(z0) for _, _, z0, _ in cases])
+
+
+@pytest.mark.parametrize("model,stencil,scheme", [("barkley", "lap5", "rk4"), ("fk", "lap9", "rk4"),
+                                                  ("bocf", "lap9_aniso", "rush_larsen")])
+@pytest.mark.parametrize("tangent", [False, True])
+def test_batched_time_steps_per_instance(model, stencil, scheme, tangent):
+    """Members with different time steps (periodic orbits of different
+    periods at a common step count) in one batched call: each equals its own
+    single call bit for bit."""
+    cases = batch_setup(model, stencil, scheme, 5, sizes=[(40, 36), (64, 50), (33, 70)])
+    probs = [pr for _, pr, _, _ in cases]
+    for k, pr in enumerate(probs):
+        pr.dt = pr.dt * (1.0 - 0.125 * k)
+    fields = [dev(z0) for _, _, z0, _ in cases]
+    tans = [dev(v) for _, _, _, v in cases] if tangent else None
+    rd.step_batched(probs, fields, tans)
+    for k, ((po, _, z0, v), pr) in enumerate(zip(cases, probs)):
+        zs, vs = dev(z0), dev(v)
+        if tangent:
+            rd.jvp(pr, zs, vs)
+        else:
+            rd.step(pr, zs)
+        assert all(np.array_equal(a, b) for a, b in zip(host(fields[k]), host(zs))), k
+        if tangent:
+            assert all(np.array_equal(a, b) for a, b in zip(host(tans[k]), host(vs))), k
+    if not tangent:
+        # and against the oracle at that member's own step
+        po = dataclasses.replace(cases[-1][0], dt=probs[-1].dt)
+        ref = oracle.step(po, cases[-1][2], 5)
+        assert rel_linf(host(fields[-1]), ref) <= 1e-11
 
 
 def test_ensemble_workload_shapes_one_step():

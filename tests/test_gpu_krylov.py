@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_1309_1720_amd as rd
 import rd_inputs as ri
 from paper_1309_1720_amd import krylov
@@ -104,3 +105,69 @@ def test_finite_difference_jvp_variant_runs_and_converges():
     print("exact", exact.residuals, exact.krylov_iterations, "fd", fd.residuals, fd.krylov_iterations)
     assert exact.residuals[-1] <= 1e-13
     assert np.isfinite(fd.residuals).all() and fd.residuals[-1] < 1e-3 * fd.residuals[0]
+
+
+def _settled_spiral(n, settle_time=300.0, scan=260):
+    """A Barkley spiral on an n x n grid (the cross-field seed, RK4 at the
+    workload's dt) after settle_time, and the step count N* in [100, scan) at
+    which the state comes closest to itself (the period estimate N* dt)."""
+    w = ri.workload("barkley_128_euler", nx=n, ny=n, scheme="rk4")
+    params = ri.params_array("barkley")
+    z = [torch.from_numpy(a).cuda() for a in ri.initial_condition(w)]
+    rd.step(rd.Problem.from_workload(w, params, nsteps=int(round(settle_time / w["dt"]))), z)
+    z0 = [a.clone() for a in z]
+    one = rd.Problem.from_workload(w, params, nsteps=1)
+    dist = []
+    for _ in range(scan):
+        rd.step(one, z)
+        dist.append(sum(float(torch.sum((a - b) ** 2).item()) for a, b in zip(z, z0)) ** 0.5)
+    nstar = 100 + int(np.argmin(dist[99:]))
+    return w, params, z0, nstar
+
+
+def _spiral_members(sizes, nsteps):
+    members = []
+    for n in sizes:
+        w, params, z0, nstar = _settled_spiral(n)
+        prob = rd.Problem.from_workload(w, params, nsteps=nsteps)
+        members.append((prob, z0, nstar * w["dt"], w))
+    return members
+
+
+def test_periodic_orbit_of_rotating_spirals():
+    """Rotating Barkley spirals on a 64^2 and the 128^2 grid, unknown
+    periods: Newton-Krylov with a phase condition, exact JVPs of both
+    members in one batched call per Krylov iteration (their time steps
+    T_i / N differ), to a relative residual <= 1e-10.  The converged orbit
+    is re-integrated by the oracle over its period and must return to
+    itself."""
+    N = 160
+    members = _spiral_members((64, 128), N)
+    probs = [m[0] for m in members]
+    out = rd.periodic_orbit(probs, [m[1] for m in members], [m[2] for m in members], tol=1e-10)
+    print("residuals", out.residuals, "krylov", out.krylov_iterations, "periods", out.periods)
+    assert out.residuals[-1] <= 1e-10
+    for (prob, z0, t0, w), fields, T in zip(members, out.states, out.periods):
+        assert abs(T - t0) <= 0.05 * t0, (T, t0)
+        u = fields[0].cpu().numpy()
+        assert u.max() > 0.9 and u.min() < 0.05  # an excited, non-uniform state
+        po = oracle.Problem.from_workload(dict(w, dt=T / N), params=ri.params_array("barkley"))
+        zs = [f.cpu().numpy() for f in fields]
+        back = oracle.step(po, zs, N)
+        num = sum(float(np.sum((a - b) ** 2)) for a, b in zip(back, zs)) ** 0.5
+        den = sum(float(np.sum(a * a)) for a in zs) ** 0.5
+        print(f"{prob.nx}^2: T = {T:.12f}, oracle return ||Phi(z) - z|| / ||z|| = {num / den:.2e}")
+        assert num / den <= 1e-10
+    # superlinear at the end: the last Newton step gains at least three orders
+    r = out.residuals
+    assert r[-1] <= 1e-3 * r[-2], r
+
+
+def test_periodic_orbit_with_fd_jvps_converges():
+    """The same solve on the 64^2 spiral with central-difference JVPs: it
+    converges too (the residual is exact), more slowly per Newton step."""
+    members = _spiral_members((64,), 160)
+    prob, z0, t0, _ = members[0]
+    fd = rd.periodic_orbit([prob], [z0], [t0], tol=1e-10, jvp="fd", fd_eps=1e-7)
+    print("fd residuals", fd.residuals, fd.krylov_iterations, fd.periods)
+    assert fd.residuals[-1] < 1e-6 * fd.residuals[0]

@@ -13,6 +13,8 @@ import paper_1309_1720_amd as rd
 import rd_inputs as ri
 from rdtest import dev, gpu_step, host, problems, rel_linf
 
+import conditioning
+
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
@@ -162,26 +164,21 @@ def test_adjoint_workload_full_horizon_dot_product():
         assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
 
 
-AUTOGRAD_CASES = [("barkley", "lap5", 80, 72), ("barkley", "lap9", 80, 72), ("barkley", "lap9_aniso", 80, 72),
-                  ("fk", "lap9", 64, 48), ("bocf", "lap9_aniso", 64, 48), ("bocf", "lap5", 48, 40)]
-
-
-@pytest.mark.parametrize("model,stencil,nx,ny", AUTOGRAD_CASES)
-def test_autograd_flow_matches_oracle_gradient(model, stencil, nx, ny):
+@pytest.mark.parametrize("case", conditioning.CASES, ids=lambda c: "-".join(map(str, c[:4])))
+def test_autograd_flow_matches_oracle_gradient(case):
     """Gradient of a loss over the first two fields through the autograd
     function, 200 RK4 steps with checkpoints every 32, against the oracle's
     adjoint given the SAME cotangent: the one torch hands to backward, formed
     from the GPU's final state.  (The two forward runs agree to rounding, not
-    bit for bit, on all operators but the 5-point one; a cotangent formed from
-    the oracle's own final state would differ by that much.)  The oracle's
-    gradient moves by 2e-14 at most when its initial state moves by one ulp
-    (test_adjoint_one_ulp_floor_over_200_steps), so 1e-11 leaves three orders
-    of margin."""
-    steps = 200
-    po, pr, z0 = setup(model, stencil, "rk4", nx, ny, steps, 32, seed=9)
-    if model == "barkley" and stencil == "lap9_aniso":
-        po = dataclasses.replace(po, D_perp=0.25, theta0=-1.0, theta1=1.0)
-        pr = dataclasses.replace(pr, D_perp=0.25, theta0=-1.0, theta1=1.0)
+    bit for bit, on these operators and models; a cotangent formed from the
+    oracle's own final state would differ by that much.)  The cases are the
+    well-conditioned ones of the conditioning module: one-ulp perturbations
+    after every step move the oracle's state and gradient by 1e-13 at most
+    over the horizon (oracle pins), two orders below the 1e-11 bar."""
+    model, stencil, nx, ny, ic = case
+    w = conditioning.workload(model, stencil, nx, ny)
+    po, pr = problems(w, nsteps=conditioning.STEPS)
+    z0 = conditioning.initial(model, nx, ny, ic)
     zs = [torch.from_numpy(a).cuda().requires_grad_(True) for a in z0]
     out = rd.flow(pr, *zs)
     uT, vT = out[0], out[1]
@@ -189,9 +186,9 @@ def test_autograd_flow_matches_oracle_gradient(model, stencil, nx, ny):
     loss.backward()
     zT = [t.detach().cpu().numpy() for t in out]
     lam = [2.0 * po.dx ** 2 * zT[0] + zT[1], zT[0]] + [np.zeros_like(a) for a in zT[2:]]
-    ref = oracle.vjp(po, z0, lam, steps, checkpoint_every=32)
+    ref = oracle.vjp(po, z0, lam, conditioning.STEPS, checkpoint_every=conditioning.EVERY)
     err = rel_linf([t.grad.cpu().numpy() for t in zs], ref)
-    print(f"{model} {stencil} {nx}x{ny} {steps} steps: gradient rel-Linf {err:.3e}")
+    print(f"{model} {stencil} {nx}x{ny} {conditioning.STEPS} steps: gradient rel-Linf {err:.3e}")
     assert err <= TOL
 
 
