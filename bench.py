@@ -441,6 +441,39 @@ def other_workloads(rd, torch, dev, only=None, steps: int = 200):
                         "krylov_iterations": res.krylov_iterations}
         out["newton_krylov_fhn_3_members_200_steps"] = nk
 
+    if only in (None, "periodic_orbit_barkley_spirals"):
+        # Newton-Krylov for the periodic orbits of rotating Barkley spirals
+        # (64^2 and 128^2, RK4, N = 160 steps per period, periods unknown),
+        # exact vs central-difference JVPs, from spirals settled for 300 time
+        # units (the period guess is the return time nearest to the state).
+        import numpy as np
+        from paper_1309_1720_amd import krylov
+        N = 160
+        members = []
+        for n in (64, 128):
+            wk = ri.workload("barkley_128_euler", nx=n, ny=n, scheme="rk4")
+            params = ri.params_array("barkley")
+            z = [torch.from_numpy(a).to(dev) for a in ri.initial_condition(wk)]
+            rd.step(rd.Problem.from_workload(wk, params, nsteps=int(round(300.0 / wk["dt"]))), z)
+            z0 = [a.clone() for a in z]
+            one = rd.Problem.from_workload(wk, params, nsteps=1)
+            dist = []
+            for _ in range(260):
+                rd.step(one, z)
+                dist.append(sum(float(torch.sum((a - b) ** 2)) for a, b in zip(z, z0)))
+            nstar = 100 + int(np.argmin(dist[99:]))
+            members.append((rd.Problem.from_workload(wk, params, nsteps=N), z0, nstar * wk["dt"]))
+        po = {"members": ["barkley 64^2 rk4", "barkley 128^2 rk4"], "steps_per_period": N}
+        for kind in ("exact", "fd"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = krylov.periodic_orbit([m[0] for m in members], [m[1] for m in members],
+                                        [m[2] for m in members], tol=1e-10, jvp=kind)
+            torch.cuda.synchronize()
+            po[kind] = {"seconds": time.perf_counter() - t0, "residuals": res.residuals,
+                        "krylov_iterations": res.krylov_iterations, "periods": res.periods}
+        out["periodic_orbit_barkley_spirals"] = po
+
     if only in (None, "fk_256cube_lap27_rk4"):
         # 3-D: Fenton-Karma 256^3, 27-point, RK4 (20 of its 1000 steps), one
         # HBM-streaming launch per stage (STAGE3_RK4_FIELDS arrays per field and cell).

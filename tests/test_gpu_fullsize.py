@@ -51,18 +51,16 @@ def test_fk_1024_thousand_steps():
     check_sample(host(zt), g, what="fk 1024^2 1000 steps")
 
 
-def test_bocf_2048_two_hundred_and_thousand_steps():
+@pytest.mark.parametrize("horizon", [200, 1000])
+def test_bocf_2048_full_grid(horizon):
     """Bueno-Orovio 2048^2, anisotropic flux form, RK4: the whole grid after
-    200 and after 1000 steps (one run, checked at both horizons)."""
+    200 and after 1000 steps."""
+    g = golden.load("bocf_2048_aniso_rk4", horizon)
     w = ri.workload("bocf_2048_aniso_rk4")
+    _, pr = problems(w, nsteps=horizon)
     zt = dev(ri.initial_condition(w))
-    done = 0
-    for T in (200, 1000):
-        g = golden.load("bocf_2048_aniso_rk4", T)
-        _, pr = problems(w, nsteps=T - done)
-        rd.step(pr, zt)
-        done = T
-        check_sample(host(zt), g, what=f"bocf 2048^2 {T} steps")
+    rd.step(pr, zt)
+    check_sample(host(zt), g, what=f"bocf 2048^2 {horizon} steps")
 
 
 def test_ensemble_jvp_one_member_per_size_two_hundred_steps():
