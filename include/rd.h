@@ -206,6 +206,28 @@ int rd_step(const rd_problem* p, double* const* fields, double* checkpoints,
             void* ws, size_t ws_bytes, void* hip_stream);
 
 /*
+ * rd_step_noalloc -- rd_step for callers that cannot allocate device memory
+ * or pass a workspace: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments and results as rd_step
+ * (bit for bit) without ws / ws_bytes: its scratch is a device array of
+ * RD_NOALLOC_SCRATCH_BYTES the library owns, one per GPU, held until the
+ * process ends.  It calls no hipMalloc / hipFree; the first call for a grid
+ * shape may time candidate plans with HIP events, as rd_step does (not
+ * during a capture).
+ *   Problems whose rd_workspace_bytes(RD_OP_STEP) exceeds
+ *   RD_NOALLOC_SCRATCH_BYTES fail with RD_EWORKSPACE (64 MiB: e.g. a
+ *   2048^2 Barkley or a 1024^2 Fenton-Karma grid fits, a 2048^2
+ *   Bueno-Orovio grid does not).
+ *   All calls on one GPU share its array: calls that may overlap on one GPU
+ *   (different streams, threads or processes' graphs replayed concurrently)
+ *   race and must be ordered by the caller.  The array keeps the last call's
+ *   contents; nothing in it needs to start at zero.
+ */
+#define RD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rd_step_noalloc(const rd_problem* p, double* const* fields, double* checkpoints,
+                    void* hip_stream);
+
+/*
  * rd_jvp -- tangent-linear map of the finite-time flow (an addition to the
  * paper, motivated by its Newton-Krylov use case, Sect. 1).  Advances the
  * state z and a tangent dz together by p->nsteps steps, in place:

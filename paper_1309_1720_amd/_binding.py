@@ -71,6 +71,7 @@ def lib() -> C.CDLL:
             "rd_checkpoint_count": ([P, C.POINTER(C.c_int64)], C.c_int),
             "rd_workspace_bytes": ([P, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
             "rd_step": ([P, _DPP, _PTR, _PTR, C.c_size_t, _PTR], C.c_int),
+            "rd_step_noalloc": ([P, _DPP, _PTR, _PTR], C.c_int),
             "rd_jvp": ([P, _DPP, _DPP, _PTR, C.c_size_t, _PTR], C.c_int),
             "rd_vjp": ([P, _PTR, _DPP, _PTR, C.c_size_t, _PTR], C.c_int),
             "rd_step_batched_workspace_bytes": ([P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)], C.c_int),
@@ -357,6 +358,25 @@ def step(prob: Problem, fields, checkpoints: torch.Tensor | None = None):
         ckpt = checkpoints.data_ptr()
     ws, wsp = _workspace(workspace_bytes(prob, "step"), dev)
     _check(L.rd_step(C.byref(cp), f, ckpt, wsp, ws.numel() if ws is not None else 0, _stream(dev)))
+    return fields
+
+
+def step_noalloc(prob: Problem, fields, checkpoints: torch.Tensor | None = None):
+    """rd_step_noalloc: rd_step with the library's own per-GPU scratch (no
+    workspace, nothing allocated); raises RDError(RD_EWORKSPACE) for grids
+    beyond its size."""
+    L = lib()
+    f = _ptrs(fields, prob, "fields")
+    dev = fields[0].device
+    cp, _buf = prob.to_c()
+    ckpt = 0
+    if checkpoints is not None:
+        need = checkpoint_count(prob) * prob.nfields * prob.cells
+        if (not checkpoints.is_cuda or checkpoints.dtype != torch.float64
+                or not checkpoints.is_contiguous() or checkpoints.numel() < need):
+            raise ValueError(f"checkpoints: need a contiguous float64 device tensor of >= {need} elements")
+        ckpt = checkpoints.data_ptr()
+    _check(L.rd_step_noalloc(C.byref(cp), f, ckpt, _stream(dev)))
     return fields
 
 
