@@ -105,7 +105,7 @@ def main_forward(out: str, workload: str, tile_rows: int) -> None:
     needle = sweep_kernel(w)
     args = f"--workload {workload} {BENCH_ARGS} --tile-rows {tile_rows}"
     cmd = lambda extra, steps: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o fwd -- "
-                                f"python3 <repo>/bench.py --steps {steps} --warmup 5 {args}")
+                                f"python3 <repo>/bench.py --steps {steps} --warmup 20 {args}")
     title = f"{w['model']} {w['nx']}x{w['ny']}, {w['stencil']}, {w['scheme']}"
 
     stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
@@ -115,10 +115,11 @@ def main_forward(out: str, workload: str, tile_rows: int) -> None:
     r = row[0]
     kname = r["Name"].split("(")[0].replace("void ", "")
     durs = _trace_durations(os.path.join(out, "stats"), needle)
-    avg = float(r["AverageNs"]) / 1e3
+    mean = float(r["AverageNs"]) / 1e3
     med = sorted(durs)[len(durs) // 2]
+    avg = med  # the launch time used below: the median dispatch (the first ones run while clocks ramp)
     lines = [f"# Fused step, {title} (FP64) — kernel timings", "",
-             "Command:", "", "    " + cmd("--kernel-trace --stats", 20), "",
+             "Command:", "", "    " + cmd("--kernel-trace --stats", 200), "",
              "| kernel | calls | avg us | median us | min us | max us | % of GPU time |",
              "|---|---|---|---|---|---|---|"]
     for q in sorted(stats, key=lambda q: -float(q["TotalDurationNs"]))[:6]:
@@ -128,7 +129,7 @@ def main_forward(out: str, workload: str, tile_rows: int) -> None:
                      f"{sorted(qd)[len(qd) // 2]:.2f} | {float(q['MinNs']) / 1e3:.2f} | "
                      f"{float(q['MaxNs']) / 1e3:.2f} | {float(q['Percentage']):.1f} |")
     lines += ["", f"Band height {tile_rows} rows.  The {r['Calls']} calls of `{kname}` are the warm-up and "
-                  f"the timed steps, one launch per step; it averages {avg:.2f} us (median {med:.2f} us) = "
+                  f"the timed steps, one launch per step; the median dispatch takes {med:.2f} us (mean {mean:.2f} us) = "
                   f"{cells / (avg * 1e-6):.3e} cell-updates/s, {alg / (avg * 1e-6) / 1e9:.0f} GB/s of "
                   f"algorithmic traffic ({bench.B_ALG[w['model']]} B per cell-update: the state read and "
                   f"written once), {alg / (avg * 1e-6) / bench.HBM_PEAK * 100:.1f}% of 8 TB/s."]
@@ -145,7 +146,7 @@ def main_forward(out: str, workload: str, tile_rows: int) -> None:
     g = {c: _pick(sq, needle, c) for c in SQ_COUNTERS}
     rec = {"kernel": kname, "workload": workload, "cells": cells,
            "kernel_sha": bench.kernel_hash(), "tile_rows": tile_rows,
-           "avg_launch_us": avg, "median_launch_us": med,
+           "mean_launch_us": mean, "median_launch_us": med,
            "fetch_kib_per_dispatch": round(f_k, 1), "write_kib_per_dispatch": round(w_k, 1),
            "calibration": {"kernel": "torch.add(src, 0.0, out=dst), 2^26 doubles",
                            "bytes_read": CALIB_BYTES, "bytes_written": CALIB_BYTES,
@@ -161,9 +162,9 @@ def main_forward(out: str, workload: str, tile_rows: int) -> None:
     waves = g["SQ_WAVES"]
     lines = [f"# Fused step, {title} — hardware counters", "",
              "Commands (each a run of its own):", "",
-             "    " + cmd("--pmc FETCH_SIZE", 20) + " --calibration-copy",
-             "    " + cmd("--pmc WRITE_SIZE", 20) + " --calibration-copy",
-             "    " + cmd("--pmc " + " ".join(SQ_COUNTERS), 20),
+             "    " + cmd("--pmc FETCH_SIZE", 200) + " --calibration-copy",
+             "    " + cmd("--pmc WRITE_SIZE", 200) + " --calibration-copy",
+             "    " + cmd("--pmc " + " ".join(SQ_COUNTERS), 200),
              f"    python3 <repo>/bench_profile.py --forward <out> {workload} {tile_rows}", "",
              "## Memory traffic (KiB per dispatch)", "",
              "| kernel | FETCH_SIZE | WRITE_SIZE |", "|---|---|---|",
@@ -177,7 +178,7 @@ def main_forward(out: str, workload: str, tile_rows: int) -> None:
     for c in SQ_COUNTERS:
         lines.append(f"| {c} | {g[c]:.4g} | {g[c] / waves:.4g} |")
     lines += ["", f"Lane-instructions per cell-update: {g['SQ_INSTS_VALU'] * 64 / cells:.0f}. VALU issue "
-                  f"rate at the {avg:.1f} us average launch: "
+                  f"rate at the {avg:.1f} us median launch: "
                   f"{g['SQ_INSTS_VALU'] * 64 / (avg * 1e-6) / bench.VALU_LANE_ISSUE_PEAK * 100:.0f}% of the "
                   f"{bench.VALU_LANE_ISSUE_PEAK / 1e12:.1f} T lane-instructions/s capacity. Share of wave "
                   f"time issuing VALU: {g['SQ_ACTIVE_INST_VALU'] / g['SQ_WAVE_CYCLES']:.2f}; waiting on "
@@ -337,6 +338,96 @@ def main_tangent(out: str, tile_rows: int) -> None:
     print("\n".join(lines))
 
 
+def _calibration(out: str):
+    """FETCH_SIZE and WRITE_SIZE scale factors from the plain copy of the
+    headline's counter runs (OUT/fetch and OUT/write hold it)."""
+    fetch = _counters(os.path.join(out, "fetch"))
+    write = _counters(os.path.join(out, "write"))
+    f_c, w_c = _pick(fetch, CALIB, "FETCH_SIZE"), _pick(write, CALIB, "WRITE_SIZE")
+    return CALIB_BYTES / 1024 / f_c, CALIB_BYTES / 1024 / w_c
+
+
+def _kernel_table(out: str, kinds, cal_dir: str, title: str, cmd):
+    """Per-kernel timing (median dispatch) and counter traffic against the
+    algorithmic bytes each launch must move.  kinds: (name prefix, role,
+    algorithmic bytes per launch)."""
+    fs, wsc = _calibration(cal_dir)
+    fetch = _counters(os.path.join(out, "fetch"))
+    write = _counters(os.path.join(out, "write"))
+    stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
+    lines = [f"# {title}", "", "Commands (each a run of its own):", "",
+             "    " + cmd("--kernel-trace --stats"), "    " + cmd("--pmc FETCH_SIZE"), "    " + cmd("--pmc WRITE_SIZE"),
+             "", f"HBM bytes: FETCH_SIZE x {fs:.3f} + WRITE_SIZE x {wsc:.3f} per dispatch (the factors a plain copy of "
+             "2^26 doubles reads in the headline's counter runs).", "",
+             "| kernel | role | calls | median us | algorithmic MB | algorithmic GB/s | of 8 TB/s | HBM MB | HBM / algorithmic |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    med = {}
+    for needle, role, alg in kinds:
+        row = [r for r in stats if r["Name"].startswith("void " + needle)]
+        if len(row) != 1:
+            raise RuntimeError(f"expected one kernel {needle!r}, found {len(row)}")
+        durs = sorted(_trace_durations(os.path.join(out, "stats"), "void " + needle))
+        m = durs[len(durs) // 2]
+        med[needle] = m
+        f_k, w_k = _pick(fetch, needle, "FETCH_SIZE"), _pick(write, needle, "WRITE_SIZE")
+        hbm = (f_k * fs + w_k * wsc) * 1024
+        lines.append(f"| `{needle}` | {role} | {row[0]['Calls']} | {m:.2f} | {alg / 1e6:.1f} | {alg / m / 1e3:.0f} | "
+                     f"{alg / m / 1e3 / 8000 * 100:.0f}% | {hbm / 1e6:.1f} | {hbm / alg:.2f} |")
+    return med, lines
+
+
+def _write(fname: str, lines) -> None:
+    with open(os.path.join(PROFILES, fname), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main_ensemble(out: str, cal_dir: str) -> None:
+    """The 64-member Fenton-Karma ensemble (16 each of 256^2 .. 768^2, RK4):
+    the batched forward and tangent kernels, from three runs of
+    `bench.py --only-workload fk_ensemble_64_jvp`."""
+    import rd_inputs as ri
+    cells = sum(w["nx"] * w["ny"] for w in ri.fk_batch_workloads(nsteps=1))
+    cmd = lambda extra: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o p -- "
+                         "python3 <repo>/bench.py --only-workload fk_ensemble_64_jvp")
+    fwd, tan = "rd::batch_sweep_kernel<2, 9, 4, 0, 0, 1>", "rd::batch_sweep_kernel<2, 9, 4, 1, 0, 1>"
+    med, lines = _kernel_table(out, [(fwd, "one RK4 step of all 64 members", 48 * cells),
+                                     (tan, "one RK4 step of all members and their tangents", 96 * cells)],
+                               cal_dir, "Batched ensemble, 64 Fenton-Karma members (9-point, RK4, FP64) — one launch "
+                               "per step", cmd)
+    lines += ["", f"{cells} cells per launch (16 each of 256^2, 384^2, 512^2, 768^2).  Algorithmic bytes: the state "
+                  "(48 B per cell) or the state and tangent (96 B) read and written once.  The tangent step costs "
+                  f"{med[tan] / med[fwd]:.2f}x the forward step."]
+    _write("ens_fk_64_members_rk4_kernel_stats.md", lines)
+
+
+def main_adjoint(out: str, cal_dir: str) -> None:
+    """The adjoint workload (Barkley 1024^2, 5-point, RK4, 4000 steps,
+    checkpoints every 64): forward with checkpoints, then per reverse step the
+    segment recompute, the stage-input sweep and the adjoint kernel, from
+    three runs of `bench.py --only-workload barkley_1024_rk4_adjoint_4000`."""
+    cells = 1024 * 1024
+    field = 8 * cells
+    cmd = lambda extra: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o p -- "
+                         "python3 <repo>/bench.py --only-workload barkley_1024_rk4_adjoint_4000")
+    adj, stg = "rd::adjoint_kernel<1, 5, 4, 0>", "rd::sweep_kernel<1, 5, 4, 2, 1, 0, 0>"
+    rec1, fwd2 = "rd::sweep_kernel<1, 5, 4, 0, 1, 0, 0>", "rd::sweep_kernel<1, 5, 4, 0, 2, 0, 0>"
+    kinds = [(rec1, "forward step, one per launch (state read and written once)", 4 * field),
+             (stg, "stage inputs Y2..Y4 of one step (reads z, writes three states)", 8 * field),
+             (adj, "one reverse step (reads z, Y2..Y4, lambda; writes lambda)", 12 * field)]
+    stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
+    if any(r["Name"].startswith("void " + fwd2) and int(r["Calls"]) > 100 for r in stats):
+        kinds.insert(0, (fwd2, "forward, two steps per launch (state read and written once)", 4 * field))
+    med, lines = _kernel_table(out, kinds, cal_dir, "Adjoint workload, Barkley 1024x1024 (5-point, RK4, FP64) — "
+                               "forward and reverse kernels", cmd)
+    fwd_step = med[fwd2] / 2 if fwd2 in med else med[rec1]
+    rev = med[adj] + med[stg] + med[rec1]
+    lines += ["", f"Per reverse step: segment recompute + stage inputs + adjoint = {rev:.1f} us, "
+                  f"{rev / fwd_step:.2f}x the forward step ({fwd_step:.2f} us).  Bytes per cell and reverse step: "
+                  "32 (recompute) + 64 (stage inputs) + 96 (adjoint) = 192, six times the forward's 32."]
+    _write("adj_barkley_1024_rk4_kernel_stats.md", lines)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "--barkley8192":
         main_barkley8192(sys.argv[2])
@@ -346,5 +437,9 @@ if __name__ == "__main__":
         main_tangent(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "--forward":
         main_forward(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+    elif sys.argv[1] == "--ensemble":
+        main_ensemble(sys.argv[2], sys.argv[3])
+    elif sys.argv[1] == "--adjoint":
+        main_adjoint(sys.argv[2], sys.argv[3])
     else:
         raise SystemExit(__doc__)

@@ -661,6 +661,40 @@ __device__ __forceinline__ double diffusion(double up, double cen, double dn, co
   }
 }
 
+// The anisotropic flux form in a row sweep: the flux through the face north
+// of row rho is the flux through the face south of row rho - 1, which the
+// same stage computed one row earlier from the same operands in the same
+// order.  CARRIED: take it from `fy` instead of recomputing it (the rows
+// rho - 1 .. rho hold no y-boundary face).  `fy` receives this row's
+// south-face flux for the next row.  Bit-identical to `diffusion`.
+template <bool EDGE, bool YEDGE, bool CARRIED>
+__device__ __forceinline__ double diffusion_flux_rows(double up, double cen, double dn, const Column& col,
+                                                      int rho, const KConst& c, double coef, double& fy) {
+  const double wC = from_west(cen), eC = from_east(cen);
+  const double eU = from_east(up);
+  const double wD = from_west(dn), eD = from_east(dn);
+  double fxe = col.dxx_e * (eC - cen) + col.dxy_e4 * ((eD + dn) - (eU + up));
+  if (EDGE && col.east) fxe = 0.0;
+  double fxw = from_west(fxe);
+  if (EDGE && col.west) fxw = 0.0;
+  const bool mw = EDGE && col.west, me = EDGE && col.east;
+  const double wCc = mw ? cen : wC, eCc = me ? cen : eC;
+  const double wDc = mw ? dn : wD, eDc = me ? dn : eD;
+  double fys = col.dxy_c4 * ((eDc + eCc) - (wDc + wCc)) + col.dyy_c * (dn - cen);
+  double fyn;
+  if constexpr (CARRIED) {
+    fyn = fy;
+  } else {
+    const double wU = from_west(up);
+    const double wUc = mw ? up : wU, eUc = me ? up : eU;
+    fyn = col.dxy_c4 * ((eCc + eUc) - (wCc + wUc)) + col.dyy_c * (cen - up);
+  }
+  if (YEDGE && !c.periodic && rho == c.ny - 1) fys = 0.0;
+  if (YEDGE && !c.periodic && rho == 0) fyn = 0.0;
+  fy = fys;
+  return ((fxe - fxw) + (fys - fyn)) * coef;
+}
+
 // The same operators with the three rows read from LDS.  Row arrays hold one
 // value per lane at index lane + 1 (a pad column on each side); il is this
 // lane's index, iw / ie the west / east neighbours after the x-mirror (equal

@@ -150,6 +150,9 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   double yu[K][NS + 1][3][ND];   // stage-s input u (du), rows (r - k NS) - s + 1 .. - s - 1
   double yg[K][NS + 1][NF];      // stage-s input, other components, row (r - k NS) - s
   double ygn[K][NS + 1][NF];     // ... produced this iteration for the row below it
+  // anisotropic flux form: the south-face flux each stage computed on the row above
+  constexpr bool CARRY = STENCIL == RD_LAP9_ANISO;
+  double fyc[K][NS + 1][ND];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
 #pragma unroll
@@ -166,6 +169,8 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
       for (int d = 0; d < ND; ++d) yu[k][s][0][d] = yu[k][s][1][d] = yu[k][s][2][d] = 0.0;
 #pragma unroll
       for (int f = 0; f < NF; ++f) yg[k][s][f] = ygn[k][s][f] = 0.0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) fyc[k][s][d] = 0.0;
     }
   }
 
@@ -286,8 +291,13 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 
         double lap[ND];
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
-          lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c, c.dcoef[d % NDF]);
+        for (int d = 0; d < ND; ++d) {
+          if constexpr (CARRY)
+            lap[d] = diffusion_flux_rows<EDGE, !STEADY, STEADY>(up[d], y[comp(d)], dn[d], col, rho, c,
+                                                                c.dcoef[d % NDF], fyc[k][s][d]);
+          else
+            lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c, c.dcoef[d % NDF]);
+        }
         double kr[NF];
         eval_rates<MODEL, TAN, HK>(c, y, kr);
 #pragma unroll
@@ -356,7 +366,10 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   // between them goes PF rows at a time with fixed slots (its rows r + q sit
   // in slot q because the ring is in order when the run starts and ends).
   using Shift = std::integral_constant<int, -1>;
-  const int ss_lo = min(c.periodic ? yA + KS : max(yA + KS, KS + 1), r_last + 1);
+  // (one iteration later with the carried face fluxes: every stage must have
+  // run on the row above its first steady row)
+  constexpr int CL = CARRY ? 1 : 0;
+  const int ss_lo = min(c.periodic ? yA + KS + CL : max(yA + KS + CL, KS + 1), r_last + 1);
   const int ss_hi = max(load_end, ss_lo);
   const int ss_end = ss_lo + (ss_hi - ss_lo) / PF * PF;
   int r = r_first;
