@@ -428,6 +428,43 @@ def main_adjoint(out: str, cal_dir: str) -> None:
     _write("adj_barkley_1024_rk4_kernel_stats.md", lines)
 
 
+def main_headline(out: str) -> None:
+    """Kernel timings of the benchmark's own headline command (default steps,
+    warm-up and timing windows, the band height of the committed counter
+    record), to set beside the launch time bench.py measures with events:
+    `rocprofv3 --kernel-trace --stats ... -- python3 bench.py --no-cpu-baseline
+    --no-jvp --no-other-workloads` into OUT."""
+    import rd_inputs as ri
+    w = ri.workload(bench.HEADLINE)
+    needle = sweep_kernel(w)
+    stats = _rows(out, "*kernel_stats.csv")
+    row = [r for r in stats if needle in r["Name"]]
+    if len(row) != 1:
+        raise RuntimeError(f"expected one kernel matching {needle!r}, found {len(row)}")
+    r = row[0]
+    durs = _trace_durations(out, needle)
+    med = sorted(durs)[len(durs) // 2]
+    cells = w["nx"] * w["ny"]
+    alg = bench.B_ALG[w["model"]] * cells
+    kname = r["Name"].split("(")[0].replace("void ", "")
+    lines = [f"# Headline benchmark command under the profiler: {w['model']} {w['nx']}x{w['ny']}, {w['stencil']}, "
+             f"{w['scheme']} (FP64)", "", "Command:", "",
+             "    cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <out> -o p -- python3 "
+             "<repo>/bench.py --no-cpu-baseline --no-jvp --no-other-workloads",
+             f"    python3 <repo>/bench_profile.py --headline <out>", "",
+             "| kernel | calls | average us | median us | min us | max us |", "|---|---|---|---|---|---|",
+             f"| `{kname}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | {med:.2f} | "
+             f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} |", "",
+             f"The calls are the warm-up and the five timed windows of 200 steps (one launch per step) at the band "
+             f"height of the committed counter record.  Average {float(r['AverageNs']) / 1e3:.2f} us = "
+             f"{alg / (float(r['AverageNs']) * 1e-9) / 1e9:.0f} GB/s of algorithmic traffic "
+             f"({alg / (float(r['AverageNs']) * 1e-9) / bench.HBM_PEAK * 100:.1f}% of 8 TB/s); bench.py's event-timed "
+             "launch time in the same run is printed in its JSON line (`roofline.avg_launch_us`)."]
+    with open(os.path.join(PROFILES, f"fwd_{bench.HEADLINE}_bench_command_stats.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "--barkley8192":
         main_barkley8192(sys.argv[2])
@@ -437,6 +474,8 @@ if __name__ == "__main__":
         main_tangent(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "--forward":
         main_forward(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+    elif sys.argv[1] == "--headline":
+        main_headline(sys.argv[2])
     elif sys.argv[1] == "--ensemble":
         main_ensemble(sys.argv[2], sys.argv[3])
     elif sys.argv[1] == "--adjoint":
