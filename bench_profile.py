@@ -404,27 +404,40 @@ def main_ensemble(out: str, cal_dir: str) -> None:
 def main_adjoint(out: str, cal_dir: str) -> None:
     """The adjoint workload (Barkley 1024^2, 5-point, RK4, 4000 steps,
     checkpoints every 64): forward with checkpoints, then per reverse step the
-    segment recompute, the stage-input sweep and the adjoint kernel, from
-    three runs of `bench.py --only-workload barkley_1024_rk4_adjoint_4000`."""
+    segment recompute and either the fused reverse step (stage inputs
+    recomputed inside it) or the stage-input sweep and the adjoint kernel,
+    from three runs of `bench.py --only-workload barkley_1024_rk4_adjoint_4000`."""
     cells = 1024 * 1024
     field = 8 * cells
     cmd = lambda extra: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o p -- "
                          "python3 <repo>/bench.py --only-workload barkley_1024_rk4_adjoint_4000")
+    fused = "rd::adjoint_fused_kernel<1, 5, 4>"
     adj, stg = "rd::adjoint_kernel<1, 5, 4, 0>", "rd::sweep_kernel<1, 5, 4, 2, 1, 0, 0>"
     rec1, fwd2 = "rd::sweep_kernel<1, 5, 4, 0, 1, 0, 0>", "rd::sweep_kernel<1, 5, 4, 0, 2, 0, 0>"
-    kinds = [(rec1, "forward step, one per launch (state read and written once)", 4 * field),
-             (stg, "stage inputs Y2..Y4 of one step (reads z, writes three states)", 8 * field),
-             (adj, "one reverse step (reads z, Y2..Y4, lambda; writes lambda)", 12 * field)]
     stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
-    if any(r["Name"].startswith("void " + fwd2) and int(r["Calls"]) > 100 for r in stats):
+    has = lambda needle, n=100: any(r["Name"].startswith("void " + needle) and int(r["Calls"]) > n for r in stats)
+    kinds = [(rec1, "forward step, one per launch (state read and written once)", 4 * field)]
+    if has(fwd2):
         kinds.insert(0, (fwd2, "forward, two steps per launch (state read and written once)", 4 * field))
+    if has(fused):
+        kinds.append((fused, "one reverse step, stage inputs recomputed (reads z and lambda; writes lambda)",
+                      6 * field))
+    else:
+        kinds += [(stg, "stage inputs Y2..Y4 of one step (reads z, writes three states)", 8 * field),
+                  (adj, "one reverse step (reads z, Y2..Y4, lambda; writes lambda)", 12 * field)]
     med, lines = _kernel_table(out, kinds, cal_dir, "Adjoint workload, Barkley 1024x1024 (5-point, RK4, FP64) — "
                                "forward and reverse kernels", cmd)
     fwd_step = med[fwd2] / 2 if fwd2 in med else med[rec1]
-    rev = med[adj] + med[stg] + med[rec1]
-    lines += ["", f"Per reverse step: segment recompute + stage inputs + adjoint = {rev:.1f} us, "
-                  f"{rev / fwd_step:.2f}x the forward step ({fwd_step:.2f} us).  Bytes per cell and reverse step: "
-                  "32 (recompute) + 64 (stage inputs) + 96 (adjoint) = 192, six times the forward's 32."]
+    if fused in med:
+        rev = med[fused] + med[rec1]
+        tail = "32 (recompute) + 48 (fused reverse step) = 80, 2.5 times the forward's 32."
+        what = "segment recompute + fused reverse step"
+    else:
+        rev = med[adj] + med[stg] + med[rec1]
+        tail = "32 (recompute) + 64 (stage inputs) + 96 (adjoint) = 192, six times the forward's 32."
+        what = "segment recompute + stage inputs + adjoint"
+    lines += ["", f"Per reverse step: {what} = {rev:.1f} us, {rev / fwd_step:.2f}x the forward step "
+                  f"({fwd_step:.2f} us).  Bytes per cell and reverse step: {tail}"]
     _write("adj_barkley_1024_rk4_kernel_stats.md", lines)
 
 

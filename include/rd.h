@@ -336,6 +336,14 @@ int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows);
  * capture.  Results do not depend on it. */
 int rd_set_autotune(int32_t enable);
 
+/* Reverse step of rd_vjp for the models with at most two fields (diffusion,
+ * Barkley, FitzHugh-Nagumo) under Heun or RK4 with no-flux boundaries:
+ * non-zero (the default) recomputes each step's stage inputs inside the
+ * adjoint kernel, 0 writes them to the workspace with a separate sweep first
+ * (the path every other model and scheme takes).  Results are bit-identical;
+ * the first moves fewer bytes. */
+int rd_set_fused_adjoint(int32_t enable);
+
 /* Enables (non-zero) or disables (0, the default) a debugging check: after
  * rd_step, rd_jvp, rd_vjp and rd_step_batched have enqueued their work, a
  * small kernel scans the fields they produced and the call returns

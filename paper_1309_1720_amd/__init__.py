@@ -8,7 +8,7 @@ device memory and streams only.
 from ._binding import (  # noqa: F401
     ABI_VERSION, LIB_PATH, MODELS, N_FIELDS, SCHEMES, STENCILS, Problem, RDError,
     checkpoint_count, get_plan, get_steps_per_launch, get_tile_rows, jvp, lib, n_fields, n_params,
-    release_workspaces, set_autotune, set_check_finite, set_kernel_variant, set_steps_per_launch, set_tile_rows, step,
+    release_workspaces, set_autotune, set_check_finite, set_fused_adjoint, set_kernel_variant, set_steps_per_launch, set_tile_rows, step,
     step_noalloc,
     step_batched, vec_gram, vec_lincomb, vjp, workspace_bytes,
 )

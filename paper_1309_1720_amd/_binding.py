@@ -78,6 +78,7 @@ def lib() -> C.CDLL:
             "rd_step_batched": ([P, C.c_int32, C.POINTER(_DPP), C.POINTER(_DPP), _PTR, C.c_size_t, _PTR], C.c_int),
             "rd_set_tile_rows": ([C.c_int32], C.c_int),
             "rd_set_autotune": ([C.c_int32], C.c_int),
+            "rd_set_fused_adjoint": ([C.c_int32], C.c_int),
             "rd_set_check_finite": ([C.c_int32], C.c_int),
             "rd_get_tile_rows": ([P, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
             "rd_set_kernel_variant": ([C.c_int32], C.c_int),
@@ -332,6 +333,12 @@ def vec_lincomb(y: torch.Tensor, beta: float, xs=(), coef=()) -> torch.Tensor:
 def set_autotune(enable: bool) -> None:
     """Enable or disable the band-height autotuner (see rd_set_autotune)."""
     _check(lib().rd_set_autotune(1 if enable else 0))
+
+
+def set_fused_adjoint(enable: bool) -> None:
+    """Whether rd_vjp recomputes stage inputs inside its adjoint kernel where
+    the model allows (see rd_set_fused_adjoint); results are bit-identical."""
+    _check(lib().rd_set_fused_adjoint(1 if enable else 0))
 
 
 def set_check_finite(enable: bool) -> None:

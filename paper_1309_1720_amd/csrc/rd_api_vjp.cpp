@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <cstring>
 
-#include "rd_adjoint.h"
+#include <atomic>
+
+#include "rd_adjoint_fused.h"
 #include "rd_host.h"
 
 namespace rd {
@@ -18,6 +20,25 @@ hipError_t launch_adjoint_kernel(int model, int stencil, int scheme, const AdjAr
     case RD_MODEL_FHN: return launch_adjoint_fhn(stencil, scheme, a, s);
   }
   return hipErrorInvalidValue;
+}
+
+static std::atomic<int> g_fused_adjoint{1};
+
+static hipError_t launch_adjoint_fused_kernel(int model, int stencil, int scheme, const AdjFusedArgs& a,
+                                              hipStream_t s) {
+  switch (model) {
+    case RD_MODEL_DIFFUSION: return launch_adjoint_fused_diffusion(stencil, scheme, a, s);
+    case RD_MODEL_BARKLEY: return launch_adjoint_fused_barkley(stencil, scheme, a, s);
+    case RD_MODEL_FHN: return launch_adjoint_fused_fhn(stencil, scheme, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Whether rd_vjp's reverse step recomputes the stage inputs in the adjoint
+// kernel (rd_adjoint_fused.h) for this problem.
+static bool fused_adjoint(const rd_problem* p) {
+  return g_fused_adjoint.load() && n_fields(p->model) <= 2 && p->bc == RD_BC_NOFLUX && !is_3d(p->stencil) &&
+         (p->scheme == RD_SCHEME_HEUN || p->scheme == RD_SCHEME_RK4);
 }
 
 // Workspace: (C - 1) recomputed states, NS - 1 stage inputs and one
@@ -36,6 +57,11 @@ int workspace_vjp(const rd_problem* p, size_t* out) {
 }  // namespace rd
 
 using namespace rd;
+
+extern "C" int rd_set_fused_adjoint(int32_t enable) {
+  g_fused_adjoint.store(enable != 0 ? 1 : 0);
+  return RD_OK;
+}
 
 extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* const* cot, void* ws,
                       size_t ws_bytes, void* hip_stream) {
@@ -106,7 +132,28 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
       for (int f = 0; f < nv; ++f) a.ys[i][f] = stage_in(i, f);
     return launch_adjoint_kernel(p->model, p->stencil, p->scheme, a, s);
   };
-  set_geometry(c, ns, tuned_rows(kTuneAdjoint, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, s, adj_trial));
+  const bool fused = fused_adjoint(p);
+  KConst cfu = c;
+  if (fused) {
+    // the fused reverse step: its own band height, tuned the same way
+    const int halo = fused_adjoint_halo(ns);
+    auto fused_trial = [&](int ty) -> hipError_t {
+      AdjFusedArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.c = c;
+      set_geometry(a.c, halo, ty);
+      for (int f = 0; f < nv; ++f) {
+        a.z[f] = ckpt(0, f);
+        a.lam_in[f] = cot[f];
+        a.lam_out[f] = lam_buf[f];
+      }
+      return launch_adjoint_fused_kernel(p->model, p->stencil, p->scheme, a, s);
+    };
+    set_geometry(cfu, halo,
+                 tuned_rows(kTuneAdjointFused, p->model, p->stencil, p->scheme, p->nx, p->ny, halo, s, fused_trial));
+  } else {
+    set_geometry(c, ns, tuned_rows(kTuneAdjoint, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, s, adj_trial));
+  }
 
   double* curA[kMaxFields];
   double* curB[kMaxFields];
@@ -142,6 +189,20 @@ extern "C" int rd_vjp(const rd_problem* p, const double* checkpoints, double* co
       if (e != hipSuccess) return hip_fail(e, "recompute step launch");
     }
     for (int64_t n = stop - 1; n >= start; --n) {
+      if (fused) {
+        AdjFusedArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.c = cfu;
+        for (int f = 0; f < nv; ++f) {
+          a.z[f] = state(n, f);
+          a.lam_in[f] = cur[f];
+          a.lam_out[f] = oth[f];
+        }
+        hipError_t e = launch_adjoint_fused_kernel(p->model, p->stencil, p->scheme, a, s);
+        if (e != hipSuccess) return hip_fail(e, "fused adjoint step launch");
+        std::swap(cur, oth);
+        continue;
+      }
       if (ns > 1) {
         SweepArgs a;
         std::memset(&a, 0, sizeof a);

@@ -21,7 +21,7 @@ void set_geometry(KConst& c, int halo, int ty);
 
 // Autotuned rows per wave band (rd_tune.cpp).  `trial(ty)` enqueues one
 // launch with that band height that writes only workspace.
-enum TuneKind { kTuneForward = 0, kTuneTangent = 1, kTuneAdjoint = 2, kTuneBatched = 3 };
+enum TuneKind { kTuneForward = 0, kTuneTangent = 1, kTuneAdjoint = 2, kTuneBatched = 3, kTuneAdjointFused = 20 };
 struct Plan {
   int variant;  // StepVariant
   int ty;       // rows per band

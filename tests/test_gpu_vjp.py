@@ -260,3 +260,28 @@ def test_adjoint_workload_central_differences_in_32_directions():
         worst = max(worst, abs(d / (2 * eps) - exact) / sigma)
     print(f"250 steps, 32 directions: max |FD - <g, v>| / sigma = {worst:.2e}")
     assert worst <= 1e-4
+
+
+FUSED_CASES = [(m, st, sc) for m in ("barkley", "fhn", "diffusion") for st in ("lap5", "lap9", "lap9_aniso")
+               for sc in ("heun", "rk4")]
+
+
+@pytest.mark.parametrize("model,stencil,scheme", FUSED_CASES)
+@pytest.mark.parametrize("nx,ny,steps,every", [(97, 61, 13, 5), (130, 70, 9, 9), (1, 9, 3, 2), (9, 1, 3, 3),
+                                               (64, 3, 4, 4)])
+def test_fused_reverse_step_equals_two_kernel_path_bitwise(model, stencil, scheme, nx, ny, steps, every):
+    """The reverse step with the stage inputs recomputed inside the adjoint
+    kernel gives the same bits as the stage-input sweep followed by the
+    adjoint kernel (and hence the oracle's results to 1e-11, see
+    test_vjp_matches_oracle)."""
+    po, pr, z0 = setup(model, stencil, scheme, nx, ny, steps, every)
+    lam = ri.direction(len(z0), nx, ny, 91)
+    try:
+        rd.set_fused_adjoint(False)
+        two = gpu_vjp(pr, z0, lam)
+    finally:
+        rd.set_fused_adjoint(True)
+    fused = gpu_vjp(pr, z0, lam)
+    assert all(np.array_equal(a, b) for a, b in zip(fused, two))
+    if (nx, ny) == (97, 61):
+        assert rel_linf(fused, oracle.vjp(po, z0, lam, steps, checkpoint_every=every)) <= TOL
