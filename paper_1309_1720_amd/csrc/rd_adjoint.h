@@ -100,12 +100,13 @@ __device__ __forceinline__ ColumnNb make_column_nb(int gx, const KConst& c) {
 // back to the cells it reads; gathered here per cell, including the cells a
 // mirrored (clamped) ghost index lands on.  up, cen, dn: a at rows J-1, J,
 // J+1 (values outside the grid are not used).  All lanes call it together.
-template <bool EDGE>
+// YEDGE = false promises 0 < J < ny - 1 (the same operations, no y-face test).
+template <bool EDGE, bool YEDGE = true>
 __device__ __forceinline__ double flux_transpose(double up, double cen, double dn, const Column& col,
                                                  const ColumnNb& nb, int J, const KConst& c, double s) {
   const bool hasW = !(EDGE && col.west), hasE = !(EDGE && col.east);  // faces I-1/2, I+1/2 exist
   const bool atW = EDGE && col.west, atE = EDGE && col.east;          // I == 0, I == nx-1
-  const bool hasU = c.periodic || J >= 1, hasD = c.periodic || J <= c.ny - 2;
+  const bool hasU = !YEDGE || c.periodic || J >= 1, hasD = !YEDGE || c.periodic || J <= c.ny - 2;
   // x-face potentials of the east face at rows J-1, J, J+1, and of the west face
   const double pe_u = up - from_east(up), pe_c = cen - from_east(cen), pe_d = dn - from_east(dn);
   const double pw_u = from_west(pe_u), pw_c = from_west(pe_c), pw_d = from_west(pe_d);

@@ -110,7 +110,14 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
     for (int f = 0; f < NV; ++f) lpre[f] = a.lam_in[f][(size_t)l_lo * nx + cx];
   }
 
-  for (int r = r_first; r <= r_last; ++r) {
+  // One iteration: take z row r and lambda row r - D, run the forward stages
+  // on rows r - s and the reverse stages on rows r - D - (S - j + 1).  STEADY
+  // marks iterations in which every stage is active and no stage row touches
+  // the y-edges: no branch, no mirror, and the stores need no row test, so the
+  // stages' independent work forms one basic block.  Loads past a range end
+  // re-read its last row (in bounds, never used).
+  auto iter = [&](int r, auto steady_tag) __attribute__((always_inline)) {
+    constexpr bool STEADY = decltype(steady_tag)::value;
     // advance the rings by one row
 #pragma unroll
     for (int q = ZD - 1; q > 0; --q)
@@ -141,32 +148,30 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
       for (int f = NDF; f < NV; ++f) kbg[j][f] = kbgn[j][f];
     }
     // z row r and lambda row r - D (rows outside their ranges are never read)
-    if (r < z_end) {
+    if (STEADY || r < z_end) {
 #pragma unroll
       for (int f = 0; f < NV; ++f) zr[0][f] = zpre[f];
-      if (r + 1 < z_end) {
-        const size_t o = (size_t)(r + 1) * nx + cx;
+      const size_t o = (size_t)min(r + 1, z_end - 1) * nx + cx;
 #pragma unroll
-        for (int f = 0; f < NV; ++f) zpre[f] = a.z[f][o];
-      }
+      for (int f = 0; f < NV; ++f) zpre[f] = a.z[f][o];
     }
     const int lrow = r - D;
-    if (lrow >= l_lo && lrow < l_end) {
+    if (STEADY || (lrow >= l_lo && lrow < l_end)) {
 #pragma unroll
       for (int f = 0; f < NV; ++f) lr[0][f] = lpre[f];
-      if (lrow + 1 < l_end) {
-        const size_t o = (size_t)(lrow + 1) * nx + cx;
+      const size_t o = (size_t)min(lrow + 1, l_end - 1) * nx + cx;
 #pragma unroll
-        for (int f = 0; f < NV; ++f) lpre[f] = a.lam_in[f][o];
-      }
+      for (int f = 0; f < NV; ++f) lpre[f] = a.lam_in[f][o];
     }
 
     // forward stages: stage s on row r - s produces Y_{s+1} there
 #pragma unroll
     for (int s = 1; s < NS; ++s) {
       const int rho = r - s;
-      const int ext = 2 * NS - 2 - s;
-      if (rho < max(yA - ext, 0) || rho >= min(yB + ext, c.ny)) continue;  // wave-uniform
+      if (!STEADY) {
+        const int ext = 2 * NS - 2 - s;
+        if (rho < max(yA - ext, 0) || rho >= min(yB + ext, c.ny)) continue;  // wave-uniform
+      }
       double y[NV], up[NDF], dn[NDF];
       if (s == 1) {
 #pragma unroll
@@ -185,14 +190,17 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
           dn[d] = yr[s][0][d];
         }
       }
+      if (!STEADY) {
 #pragma unroll
-      for (int d = 0; d < NDF; ++d) {
-        if (rho == 0) up[d] = y[d];
-        if (rho == c.ny - 1) dn[d] = y[d];
+        for (int d = 0; d < NDF; ++d) {
+          if (rho == 0) up[d] = y[d];
+          if (rho == c.ny - 1) dn[d] = y[d];
+        }
       }
       double lap[NDF];
 #pragma unroll
-      for (int d = 0; d < NDF; ++d) lap[d] = diffusion<STENCIL, EDGE>(up[d], y[d], dn[d], col, rho, c, c.dcoef[d]);
+      for (int d = 0; d < NDF; ++d)
+        lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[d], dn[d], col, rho, c, c.dcoef[d]);
       double kr[NV];
       eval_rates<MODEL, false>(c, y, kr);
 #pragma unroll
@@ -207,7 +215,7 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
     for (int j = NS; j >= 1; --j) {
       const int lag = NS - j + 1;
       const int rho = r - D - lag;
-      if (rho < max(yA - (j - 1), 0) || rho >= min(yB + (j - 1), c.ny)) continue;  // wave-uniform
+      if (!STEADY && (rho < max(yA - (j - 1), 0) || rho >= min(yB + (j - 1), c.ny))) continue;  // wave-uniform
 
       double kb[NV], up[NDF], dn[NDF];
       if (j == NS) {
@@ -232,12 +240,14 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
       double lapT[NDF];
 #pragma unroll
       for (int d = 0; d < NDF; ++d) {
-        if (rho == 0) up[d] = kb[d];
-        if (rho == c.ny - 1) dn[d] = kb[d];
+        if (!STEADY) {
+          if (rho == 0) up[d] = kb[d];
+          if (rho == c.ny - 1) dn[d] = kb[d];
+        }
         if constexpr (ANISO)
-          lapT[d] = flux_transpose<EDGE>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d]);
+          lapT[d] = flux_transpose<EDGE, !STEADY>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d]);
         else
-          lapT[d] = diffusion<STENCIL, EDGE>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d]);
+          lapT[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d]);
       }
       // Y_j at row rho: z for j = 1 (age 2S - 2), else produced 2S - 2j iterations ago
       double y[NV];
@@ -261,13 +271,31 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
         for (int d = 0; d < NDF; ++d) kbu[j - 1][0][d] = b * lr[lag][d] + aj * yb[d];
 #pragma unroll
         for (int f = NDF; f < NV; ++f) kbgn[j - 1][f] = b * lr[lag][f] + aj * yb[f];
-      } else if (out_col && rho >= yA && rho < yB) {
+      } else if (out_col && (STEADY || (rho >= yA && rho < yB))) {
         const size_t oo = (size_t)rho * nx + gx;
 #pragma unroll
         for (int f = 0; f < NV; ++f) a.lam_out[f][oo] = lacc[lag - 1][f];
       }
     }
+  };
+
+  // Steady iterations: r >= yA + 2S - 2 and r >= 2S - 1 (the last reverse
+  // stage's row is in the band and not row 0), r < min(yB + 2S - 2, ny) (the
+  // first forward stage's row is not row ny - 1 and every stage's row is
+  // before its range end).  The steady run goes kUnroll rows at a time, so the
+  // ring shifts become register renaming inside the unrolled body.
+  constexpr int kUnroll = NS == 2 ? 4 : 2;
+  const int ss_lo = min(max(yA + 2 * NS - 2, 2 * NS - 1), r_last + 1);
+  const int ss_hi = max(min(yB + 2 * NS - 2, c.ny), ss_lo);
+  const int ss_end = ss_lo + (ss_hi - ss_lo) / kUnroll * kUnroll;
+  int r = r_first;
+  for (; r < ss_lo; ++r) iter(r, std::false_type{});
+  for (; r < ss_end; r += kUnroll) {
+#pragma unroll
+    for (int q = 0; q < kUnroll; ++q) iter(r + q, std::true_type{});
   }
+  for (; r < ss_hi; ++r) iter(r, std::true_type{});
+  for (; r <= r_last; ++r) iter(r, std::false_type{});
 }
 
 template <int MODEL, int STENCIL, int NS>
