@@ -76,7 +76,7 @@ template <int MODEL, int STENCIL, int NS, int MODE, int K = 1> struct SweepOccup
   static constexpr bool heavy = MODEL == RD_MODEL_BOCF && STENCIL == RD_LAP9_ANISO;
   static constexpr int value = K > 1                ? 2
                                : MODE == kModeTangent ? (NS == 4 || (NS == 2 && MODEL == RD_MODEL_BOCF) ? 1 : 2)
-                               : NS == 4            ? (heavy ? 1 : 2)
+                               : NS == 4            ? 2
                                : NS == 2 && heavy   ? 2
                                                     : 3;
 };
@@ -89,6 +89,13 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for<N, I + 1>(f);
   }
 }
+
+// Waves per workgroup of the sweep kernels (consecutive bands of a strip).
+constexpr int kSweepWaves = 4;
+
+// Kernel variants of the fused step (identical results): one wave carrying
+// every stage (rd_sweep.h) or one wave per stage (rd_pipe.h).
+enum StepVariant { kVariantSweep = 0, kVariantPipe = 1 };
 
 // Rows of the state loaded ahead of use (deeper where the per-row arithmetic
 // is short and registers are plentiful).
@@ -199,9 +206,18 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   // prefetch ring shifts by one row (pre[0] is row r); SLOT = q: the loop is
   // unrolled by PF and slot q holds row r, so no prefetched register is read
   // before its turn (a shift would wait for the youngest load).
-  auto iter = [&](int r, auto steady_tag, auto slot_tag) __attribute__((always_inline)) {
+  //
+  // PHASE = 1 + i: ramp-up iteration i (row yA - KS + i) of a band away from
+  // the y-edges, where which stages run is known at compile time (copy k runs
+  // stage s from i = 2 (k NS + s) on).  Such iterations, like the steady
+  // ones, test no ranges, apply no y-mirror and store without a row test;
+  // PHASE = 0 is the general ramp iteration.
+  auto iter = [&](int r, auto steady_tag, auto slot_tag, auto phase_tag) __attribute__((always_inline)) {
     constexpr bool STEADY = decltype(steady_tag)::value;
     constexpr int SLOT = decltype(slot_tag)::value;
+    constexpr int PHASE = STEADY ? 0 : decltype(phase_tag)::value;
+    constexpr bool UP = PHASE > 0;
+    constexpr bool FIXED = STEADY || UP;
     // Advance the register rings by one row.
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -225,7 +241,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
           if (!diffusive(f)) yg[k][s][f] = ygn[k][s][f];
       }
     }
-    if (STEADY || r < load_end) {
+    if (FIXED || r < load_end) {
       constexpr int q = SLOT < 0 ? 0 : SLOT;
 #pragma unroll
       for (int f = 0; f < NF; ++f) zr[0][0][f] = pre[q][f];
@@ -255,7 +271,9 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
       for (int s = 1; s <= NS; ++s) {
         if (STAGES && s == NS) continue;  // k_NS is not a stage input
         const int rho = r - k * NS - s;
-        if (!STEADY) {
+        if (UP) {
+          if (PHASE - 1 < 2 * (k * NS + s)) continue;  // folded
+        } else if (!STEADY) {
           const int lo = c.periodic ? yA - (K - k) * NS + s : max(yA - (K - k) * NS + s, 0);
           const int hi = c.periodic ? yB + (K - k) * NS - s : min(yB + (K - k) * NS - s, c.ny);
           if (rho < lo || rho >= hi) continue;  // wave-uniform
@@ -281,7 +299,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
             dn[d] = yu[k][s][0][d];
           }
         }
-        if (!STEADY) {
+        if (!FIXED) {
 #pragma unroll
           for (int d = 0; d < ND; ++d) {
             if (!c.periodic && rho == 0) up[d] = y[comp(d)];
@@ -293,19 +311,19 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
           if constexpr (CARRY)
-            lap[d] = diffusion_flux_rows<EDGE, !STEADY, STEADY>(up[d], y[comp(d)], dn[d], col, rho, c,
-                                                                c.dcoef[d % NDF], fyc[k][s][d]);
+            lap[d] = diffusion_flux_rows<EDGE, !FIXED, STEADY>(up[d], y[comp(d)], dn[d], col, rho, c,
+                                                               c.dcoef[d % NDF], fyc[k][s][d]);
           else
-            lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[comp(d)], dn[d], col, rho, c, c.dcoef[d % NDF]);
+            lap[d] = diffusion<STENCIL, EDGE, !FIXED>(up[d], y[comp(d)], dn[d], col, rho, c, c.dcoef[d % NDF]);
         }
         double kr[NF];
         eval_rates<MODEL, TAN, HK>(c, y, kr);
 #pragma unroll
         for (int d = 0; d < ND; ++d) kr[comp(d)] = lap[d] + kr[comp(d)];
 
-        // the last stage's row lies inside the band in every steady iteration
+        // the last stage's row lies inside the band in every steady or fixed iteration
         const bool last = k == K - 1;
-        const bool last_core = out_col && (STEADY || (rho >= yA && rho < yB));
+        const bool last_core = out_col && (FIXED || (rho >= yA && rho < yB));
         if (NS == 1) {
           if (STAGES) continue;
           double zn[NF];
@@ -372,17 +390,25 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   const int ss_lo = min(c.periodic ? yA + KS + CL : max(yA + KS + CL, KS + 1), r_last + 1);
   const int ss_hi = max(load_end, ss_lo);
   const int ss_end = ss_lo + (ss_hi - ss_lo) / PF * PF;
+  using Gen = std::integral_constant<int, 0>;
+  // Fixed ramp-up: rows r_first = yA - KS .. ss_lo - 1 lie at least one row
+  // inside both y-edges (stage rows yA - KS + s .. yA + KS + CL - 2), and
+  // every stage row is before its range end.
+  const bool fixed_up = !c.periodic && yA >= KS && yA + 2 * KS + 1 < c.ny;
   int r = r_first;
-  for (; r < ss_lo; ++r) iter(r, std::false_type{}, Shift{});
+  if (fixed_up) {
+    static_for<2 * KS + CL>([&](auto i) {
+      constexpr int I = decltype(i)::value;
+      iter(r_first + I, std::false_type{}, Shift{}, std::integral_constant<int, 1 + I>{});
+    });
+    r = ss_lo;  // = yA + KS + CL here
+  }
+  for (; r < ss_lo; ++r) iter(r, std::false_type{}, Shift{}, Gen{});
   for (; r < ss_end; r += PF) {
-    static_for<PF>([&](auto q) { iter(r + q, std::true_type{}, q); });
+    static_for<PF>([&](auto q) { iter(r + q, std::true_type{}, q, Gen{}); });
   }
-  for (; r <= r_last; ++r) {
-    if (r < ss_hi)
-      iter(r, std::true_type{}, Shift{});
-    else
-      iter(r, std::false_type{}, Shift{});
-  }
+  for (; r < ss_hi; ++r) iter(r, std::true_type{}, Shift{}, Gen{});
+  for (; r <= r_last; ++r) iter(r, std::false_type{}, Shift{}, Gen{});
 }
 
 // Strips that touch the grid's x-edges apply the mirror; interior strips skip it.
@@ -410,8 +436,8 @@ void sweep_kernel(SweepArgs a) {
 template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE, int HK>
 hipError_t launch_sweep_k(const SweepArgs& a, hipStream_t stream) {
   const int waves = a.c.nsx * a.c.nby;
-  const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE, K, GATE, HK>), dim3(blocks), dim3(256), 0, stream,
+  const int blocks = (waves + kSweepWaves - 1) / kSweepWaves;
+  hipLaunchKernelGGL((sweep_kernel<MODEL, STENCIL, NS, MODE, K, GATE, HK>), dim3(blocks), dim3(kSweepWaves * kWave), 0, stream,
                      a);
   return hipGetLastError();
 }
@@ -520,10 +546,6 @@ RD_DECLARE_PIPE(stg, fk)
 RD_DECLARE_PIPE(stg, bocf)
 RD_DECLARE_PIPE(stg, fhn)
 #undef RD_DECLARE_PIPE
-
-// Kernel variants of the fused step (identical results): one wave carrying
-// every stage (rd_sweep.h) or one wave per stage (rd_pipe.h).
-enum StepVariant { kVariantSweep = 0, kVariantPipe = 1 };
 
 // Dispatch over models.
 hipError_t launch_sweep_mode(int mode, int model, int stencil, int scheme, const SweepArgs& a,

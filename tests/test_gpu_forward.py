@@ -71,7 +71,7 @@ def test_kernel_variants_and_band_heights_agree_bitwise(model, stencil, scheme):
     try:
         for v in ("sweep", "pipe"):
             rd.set_kernel_variant(v)
-            for rows in (1, 4, 13, 97):
+            for rows in (1, 4, 6, 13, 97):
                 rd.set_tile_rows(rows)
                 outs.append(gpu_step(pr, z0))
     finally:
