@@ -97,17 +97,27 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
     for (int d = 0; d < NDF; ++d) kbu[j][0][d] = kbu[j][1][d] = kbu[j][2][d] = 0.0;
   }
 
-  // one row ahead: z row r + 1 and lambda row (r - D) + 1
-  double zpre[NV], lpre[NV];
+  // Rows loaded ahead, as many as the steady run is unrolled: when iteration r
+  // starts, zpre[p] holds z row r + p and lpre[p] lambda row (r - D) + p (the
+  // first lambda row is the band's l_lo, taken when r - D reaches it); loads
+  // past a range end re-read its last row.
+  constexpr int kAhead = NS == 2 ? 4 : 2;
+  double zpre[kAhead][NV], lpre[kAhead][NV];
 #pragma unroll
-  for (int f = 0; f < NV; ++f) zpre[f] = lpre[f] = 0.0;
+  for (int p = 0; p < kAhead; ++p)
+#pragma unroll
+    for (int f = 0; f < NV; ++f) zpre[p][f] = lpre[p][f] = 0.0;
   if (r_first < z_end) {
 #pragma unroll
-    for (int f = 0; f < NV; ++f) zpre[f] = a.z[f][(size_t)r_first * nx + cx];
-  }
-  if (l_lo < l_end) {  // the band's first lambda row, taken when r - D reaches it
+    for (int p = 0; p < kAhead; ++p)
 #pragma unroll
-    for (int f = 0; f < NV; ++f) lpre[f] = a.lam_in[f][(size_t)l_lo * nx + cx];
+      for (int f = 0; f < NV; ++f) zpre[p][f] = a.z[f][(size_t)min(r_first + p, z_end - 1) * nx + cx];
+  }
+  if (l_lo < l_end) {
+#pragma unroll
+    for (int p = 0; p < kAhead; ++p)
+#pragma unroll
+      for (int f = 0; f < NV; ++f) lpre[p][f] = a.lam_in[f][(size_t)min(l_lo + p, l_end - 1) * nx + cx];
   }
 
   // One iteration: take z row r and lambda row r - D, run the forward stages
@@ -115,9 +125,21 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
   // marks iterations in which every stage is active and no stage row touches
   // the y-edges: no branch, no mirror, and the stores need no row test, so the
   // stages' independent work forms one basic block.  Loads past a range end
-  // re-read its last row (in bounds, never used).
-  auto iter = [&](int r, auto steady_tag) __attribute__((always_inline)) {
+  // re-read its last row (in bounds, never used).  PHASE = 1 + i: ramp-up
+  // iteration i (row yA - (2S - 2) + i) of a band away from the y-edges, where
+  // which stages run is known at compile time: lambda from i = 2S - 4, forward
+  // stage s from i = 2s, reverse stage j from i = 4S - 2j - 2 (never j = 1);
+  // like the steady ones, such iterations test no ranges and apply no mirror.
+  // SLOT < 0: the prefetch rings shift by one row and this iteration loads
+  // the row kAhead ahead; SLOT = q: iteration q of an unrolled steady block,
+  // whose rows slot q holds (the block loads the next block's rows itself).
+  auto iter = [&](int r, auto steady_tag, auto phase_tag, auto slot_tag) __attribute__((always_inline)) {
     constexpr bool STEADY = decltype(steady_tag)::value;
+    constexpr int SLOT = decltype(slot_tag)::value;
+    constexpr int Q = SLOT < 0 ? 0 : SLOT;
+    constexpr int PHASE = STEADY ? 0 : decltype(phase_tag)::value;
+    constexpr bool UP = PHASE > 0;
+    constexpr bool FIXED = STEADY || UP;
     // advance the rings by one row
 #pragma unroll
     for (int q = ZD - 1; q > 0; --q)
@@ -148,27 +170,41 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
       for (int f = NDF; f < NV; ++f) kbg[j][f] = kbgn[j][f];
     }
     // z row r and lambda row r - D (rows outside their ranges are never read)
-    if (STEADY || r < z_end) {
+    if (FIXED || r < z_end) {
 #pragma unroll
-      for (int f = 0; f < NV; ++f) zr[0][f] = zpre[f];
-      const size_t o = (size_t)min(r + 1, z_end - 1) * nx + cx;
+      for (int f = 0; f < NV; ++f) zr[0][f] = zpre[Q][f];
+      if constexpr (SLOT < 0) {
 #pragma unroll
-      for (int f = 0; f < NV; ++f) zpre[f] = a.z[f][o];
+        for (int p = 0; p + 1 < kAhead; ++p)
+#pragma unroll
+          for (int f = 0; f < NV; ++f) zpre[p][f] = zpre[p + 1][f];
+        const size_t o = (size_t)min(r + kAhead, z_end - 1) * nx + cx;
+#pragma unroll
+        for (int f = 0; f < NV; ++f) zpre[kAhead - 1][f] = a.z[f][o];
+      }
     }
     const int lrow = r - D;
-    if (STEADY || (lrow >= l_lo && lrow < l_end)) {
+    if (STEADY || (UP ? PHASE - 1 >= 2 * NS - 4 : (lrow >= l_lo && lrow < l_end))) {
 #pragma unroll
-      for (int f = 0; f < NV; ++f) lr[0][f] = lpre[f];
-      const size_t o = (size_t)min(lrow + 1, l_end - 1) * nx + cx;
+      for (int f = 0; f < NV; ++f) lr[0][f] = lpre[Q][f];
+      if constexpr (SLOT < 0) {
 #pragma unroll
-      for (int f = 0; f < NV; ++f) lpre[f] = a.lam_in[f][o];
+        for (int p = 0; p + 1 < kAhead; ++p)
+#pragma unroll
+          for (int f = 0; f < NV; ++f) lpre[p][f] = lpre[p + 1][f];
+        const size_t o = (size_t)min(lrow + kAhead, l_end - 1) * nx + cx;
+#pragma unroll
+        for (int f = 0; f < NV; ++f) lpre[kAhead - 1][f] = a.lam_in[f][o];
+      }
     }
 
     // forward stages: stage s on row r - s produces Y_{s+1} there
 #pragma unroll
     for (int s = 1; s < NS; ++s) {
       const int rho = r - s;
-      if (!STEADY) {
+      if (UP) {
+        if (PHASE - 1 < 2 * s) continue;  // folded
+      } else if (!STEADY) {
         const int ext = 2 * NS - 2 - s;
         if (rho < max(yA - ext, 0) || rho >= min(yB + ext, c.ny)) continue;  // wave-uniform
       }
@@ -190,7 +226,7 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
           dn[d] = yr[s][0][d];
         }
       }
-      if (!STEADY) {
+      if (!FIXED) {
 #pragma unroll
         for (int d = 0; d < NDF; ++d) {
           if (rho == 0) up[d] = y[d];
@@ -200,7 +236,7 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
       double lap[NDF];
 #pragma unroll
       for (int d = 0; d < NDF; ++d)
-        lap[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], y[d], dn[d], col, rho, c, c.dcoef[d]);
+        lap[d] = diffusion<STENCIL, EDGE, !FIXED>(up[d], y[d], dn[d], col, rho, c, c.dcoef[d]);
       double kr[NV];
       eval_rates<MODEL, false>(c, y, kr);
 #pragma unroll
@@ -215,7 +251,11 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
     for (int j = NS; j >= 1; --j) {
       const int lag = NS - j + 1;
       const int rho = r - D - lag;
-      if (!STEADY && (rho < max(yA - (j - 1), 0) || rho >= min(yB + (j - 1), c.ny))) continue;  // wave-uniform
+      if (UP) {
+        if (PHASE - 1 < 4 * NS - 2 * j - 2) continue;  // folded
+      } else if (!STEADY && (rho < max(yA - (j - 1), 0) || rho >= min(yB + (j - 1), c.ny))) {
+        continue;  // wave-uniform
+      }
 
       double kb[NV], up[NDF], dn[NDF];
       if (j == NS) {
@@ -240,14 +280,14 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
       double lapT[NDF];
 #pragma unroll
       for (int d = 0; d < NDF; ++d) {
-        if (!STEADY) {
+        if (!FIXED) {
           if (rho == 0) up[d] = kb[d];
           if (rho == c.ny - 1) dn[d] = kb[d];
         }
         if constexpr (ANISO)
-          lapT[d] = flux_transpose<EDGE, !STEADY>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d]);
+          lapT[d] = flux_transpose<EDGE, !FIXED>(up[d], kb[d], dn[d], col, nb, rho, c, c.dcoef[d]);
         else
-          lapT[d] = diffusion<STENCIL, EDGE, !STEADY>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d]);
+          lapT[d] = diffusion<STENCIL, EDGE, !FIXED>(up[d], kb[d], dn[d], col, rho, c, c.dcoef[d]);
       }
       // Y_j at row rho: z for j = 1 (age 2S - 2), else produced 2S - 2j iterations ago
       double y[NV];
@@ -271,7 +311,7 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
         for (int d = 0; d < NDF; ++d) kbu[j - 1][0][d] = b * lr[lag][d] + aj * yb[d];
 #pragma unroll
         for (int f = NDF; f < NV; ++f) kbgn[j - 1][f] = b * lr[lag][f] + aj * yb[f];
-      } else if (out_col && (STEADY || (rho >= yA && rho < yB))) {
+      } else if (out_col && (FIXED || (rho >= yA && rho < yB))) {
         const size_t oo = (size_t)rho * nx + gx;
 #pragma unroll
         for (int f = 0; f < NV; ++f) a.lam_out[f][oo] = lacc[lag - 1][f];
@@ -284,18 +324,50 @@ __device__ __forceinline__ void adjoint_fused_wave(const AdjFusedArgs& a, int wi
   // first forward stage's row is not row ny - 1 and every stage's row is
   // before its range end).  The steady run goes kUnroll rows at a time, so the
   // ring shifts become register renaming inside the unrolled body.
-  constexpr int kUnroll = NS == 2 ? 4 : 2;
+  constexpr int kUnroll = kAhead;
+  using Shift = std::integral_constant<int, -1>;
   const int ss_lo = min(max(yA + 2 * NS - 2, 2 * NS - 1), r_last + 1);
   const int ss_hi = max(min(yB + 2 * NS - 2, c.ny), ss_lo);
   const int ss_end = ss_lo + (ss_hi - ss_lo) / kUnroll * kUnroll;
+  using Gen = std::integral_constant<int, 0>;
+  // Fixed ramp-up: r_first = yA - (2S - 2) and ss_lo = yA + 2S - 2, and every
+  // stage row of the ramp lies at least one row inside both y-edges.
+  const bool fixed_up = yA >= 2 * NS - 2 && yA + 4 * NS < c.ny;
   int r = r_first;
-  for (; r < ss_lo; ++r) iter(r, std::false_type{});
-  for (; r < ss_end; r += kUnroll) {
-#pragma unroll
-    for (int q = 0; q < kUnroll; ++q) iter(r + q, std::true_type{});
+  if (fixed_up) {
+    static_for<4 * NS - 4>([&](auto i) {
+      constexpr int I = decltype(i)::value;
+      iter(r_first + I, std::false_type{}, std::integral_constant<int, 1 + I>{}, Shift{});
+    });
+    r = ss_lo;
   }
-  for (; r < ss_hi; ++r) iter(r, std::true_type{});
-  for (; r <= r_last; ++r) iter(r, std::false_type{});
+  for (; r < ss_lo; ++r) iter(r, std::false_type{}, Gen{}, Shift{});
+  for (; r < ss_end; r += kUnroll) {
+    // the next block's rows, issued before this block's arithmetic: the copy
+    // into the slots at the end of the block then finds them landed (the
+    // compiler does not keep loaded registers in place across the back edge)
+    double nz[kAhead][NV], nl[kAhead][NV];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      const size_t oz = (size_t)min(r + kAhead + q, z_end - 1) * nx + cx;
+      const size_t ol = (size_t)min(r - D + kAhead + q, l_end - 1) * nx + cx;
+#pragma unroll
+      for (int f = 0; f < NV; ++f) {
+        nz[q][f] = a.z[f][oz];
+        nl[q][f] = a.lam_in[f][ol];
+      }
+    }
+    static_for<kUnroll>([&](auto q) { iter(r + q, std::true_type{}, Gen{}, q); });
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q)
+#pragma unroll
+      for (int f = 0; f < NV; ++f) {
+        zpre[q][f] = nz[q][f];
+        lpre[q][f] = nl[q][f];
+      }
+  }
+  for (; r < ss_hi; ++r) iter(r, std::true_type{}, Gen{}, Shift{});
+  for (; r <= r_last; ++r) iter(r, std::false_type{}, Gen{}, Shift{});
 }
 
 template <int MODEL, int STENCIL, int NS>
