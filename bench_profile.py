@@ -251,7 +251,7 @@ def main_barkley8192(out: str) -> None:
     """Timed-phase launches only: the trace's last 16 dispatches of the
     two-step sweep (the benchmark times two repetitions of 8 launches; the
     earlier dispatches are warm-up and the tuner's trials)."""
-    kern = "rd::sweep_kernel<1, 5, 4, 0, 2, 0>"
+    kern = "rd::sweep_kernel<1, 5, 4, 0, 2, 0, 0>"
     cells = 8192 * 8192
     cmd = lambda extra: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o bk -- "
                          "python3 <repo>/bench.py --only-workload barkley_8192_rk4_beyond_llc")
@@ -289,7 +289,7 @@ def main_barkley8192(out: str) -> None:
     print("\n".join(lines))
 
 
-TANGENT_KERNEL = "rd::sweep_kernel<2, 9, 4, 1, 1, 0>"
+TANGENT_KERNEL = "rd::sweep_kernel<2, 9, 4, 1, 1, 0, 1>"
 
 
 def main_tangent(out: str, tile_rows: int) -> None:
