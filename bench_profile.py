@@ -105,7 +105,7 @@ def main_forward(out: str, workload: str, tile_rows: int) -> None:
     needle = sweep_kernel(w)
     args = f"--workload {workload} {BENCH_ARGS} --tile-rows {tile_rows}"
     cmd = lambda extra, steps: (f"cd /tmp && rocprofv3 {extra} --output-format csv -d <out> -o fwd -- "
-                                f"python3 <repo>/bench.py --steps {steps} --warmup 20 {args}")
+                                f"python3 <repo>/bench.py --steps {steps} --warmup 400 {args}")
     title = f"{w['model']} {w['nx']}x{w['ny']}, {w['stencil']}, {w['scheme']}"
 
     stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
