@@ -115,7 +115,10 @@ template <int MODEL, int NS, int MODE> struct SweepPrefetch {
 // of z_{n+k} (the row copy k - 1 finished in the same iteration; copy 0 the
 // row just loaded) and runs its stage s on row r - k NS - s, so the launch
 // needs KS = K NS halo columns and ramp rows.
-template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1, int GATE = 0, int HK = kHkAny>
+// FR: ramp-up iterations with compile-time stage activity (below); off where
+// the larger code would not stay in the instruction cache.
+template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1, int GATE = 0, int HK = kHkAny,
+          bool FR = true>
 __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double* const* out,
                                                 double* const (*ys)[kMaxFields], const KConst& c,
                                                 int wid) {
@@ -391,36 +394,55 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   const int ss_hi = max(load_end, ss_lo);
   const int ss_end = ss_lo + (ss_hi - ss_lo) / PF * PF;
   using Gen = std::integral_constant<int, 0>;
+  int r = r_first;
+  if constexpr (!FR) {
+    for (; r < ss_lo; ++r) iter(r, std::false_type{}, Shift{}, Gen{});
+    for (; r < ss_end; r += PF) {
+      static_for<PF>([&](auto q) { iter(r + q, std::true_type{}, q, Gen{}); });
+    }
+    for (; r <= r_last; ++r) {
+      if (r < ss_hi)
+        iter(r, std::true_type{}, Shift{}, Gen{});
+      else
+        iter(r, std::false_type{}, Shift{}, Gen{});
+    }
+    return;
+  }
   // Fixed ramp-up: rows r_first = yA - KS .. ss_lo - 1 lie at least one row
   // inside both y-edges (stage rows yA - KS + s .. yA + KS + CL - 2), and
   // every stage row is before its range end.
-  const bool fixed_up = !c.periodic && yA >= KS && yA + 2 * KS + 1 < c.ny;
-  int r = r_first;
-  if (fixed_up) {
+  if (!c.periodic && yA >= KS && yA + 2 * KS + 1 < c.ny) {
     static_for<2 * KS + CL>([&](auto i) {
       constexpr int I = decltype(i)::value;
       iter(r_first + I, std::false_type{}, Shift{}, std::integral_constant<int, 1 + I>{});
     });
     r = ss_lo;  // = yA + KS + CL here
   }
+  // The steady run goes SU rows at a time: PF (slot q holds row r + q), and
+  // at least two, so that the ring shifts become register renaming even
+  // where one row is prefetched.
+  constexpr int SU = PF > 1 ? PF : 2;
+  const int su_end = ss_lo + (ss_hi - ss_lo) / SU * SU;
   for (; r < ss_lo; ++r) iter(r, std::false_type{}, Shift{}, Gen{});
-  for (; r < ss_end; r += PF) {
-    static_for<PF>([&](auto q) { iter(r + q, std::true_type{}, q, Gen{}); });
+  for (; r < su_end; r += SU) {
+    static_for<SU>([&](auto q) {
+      iter(r + q, std::true_type{}, std::integral_constant<int, decltype(q)::value % PF>{}, Gen{});
+    });
   }
   for (; r < ss_hi; ++r) iter(r, std::true_type{}, Shift{}, Gen{});
   for (; r <= r_last; ++r) iter(r, std::false_type{}, Shift{}, Gen{});
 }
 
 // Strips that touch the grid's x-edges apply the mirror; interior strips skip it.
-template <int MODEL, int STENCIL, int NS, int MODE, int K = 1, int GATE = 0, int HK = kHkAny>
+template <int MODEL, int STENCIL, int NS, int MODE, int K = 1, int GATE = 0, int HK = kHkAny, bool FR = true>
 __device__ __forceinline__ void sweep_wave(const double* const* in, double* const* out,
                                            double* const (*ys)[kMaxFields], const KConst& c,
                                            int wid) {
   const int x0 = (wid / c.nby) * (kWave - 2 * K * NS) - K * NS;
   if (strip_touches_edge(x0, c))
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR>(in, out, ys, c, wid);
   else
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK>(in, out, ys, c, wid);
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK, FR>(in, out, ys, c, wid);
 }
 
 template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE, int HK>
