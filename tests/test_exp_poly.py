@@ -101,3 +101,43 @@ def test_coefficients_are_the_committed_remez_fit():
     assert float(worst) < 3e-17
     fitted = [float(c) for c in reversed(h)]  # r^11 first, as the header
     assert constants_cached[4][:9] == fitted
+
+
+def recip_source() -> str:
+    with open(os.path.join(CSRC, "rd_device.h")) as fh:
+        src = fh.read()
+    i = src.index("__device__ __forceinline__ double recip(double d)")
+    return src[i:src.index("\n}\n", i)]
+
+
+def recip_emulated(d: float, delta: float) -> float:
+    """The device reciprocal from a hardware estimate 1/d (1 + delta): one
+    third-order step r + r (e + e^2), e = 1 - d r, in correctly rounded FMAs."""
+    with mp.workdps(60):
+        r = float(1 / mp.mpf(d) * (1 + mp.mpf(delta)))
+    e = fma(-d, r, 1.0)
+    return fma(r, fma(e, e, e), r)
+
+
+def test_recip_is_the_estimate_and_one_third_order_step():
+    body = recip_source()
+    assert "__builtin_amdgcn_rcp(d)" in body
+    assert body.count("fma(") == 3
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_recip_within_one_ulp_from_any_estimate_within_3e_8(seed):
+    """The hardware estimate is within 2.8e-8 relative (measured over 4 M
+    inputs on the GPU); from anywhere within 3e-8 the refined value is within
+    one ulp of 1/d over the divisors the reactions use (1e-4 .. 1e7)."""
+    rng = random.Random(seed)
+    worst = 0.0
+    for _ in range(1500):
+        d = math.ldexp(rng.uniform(1.0, 2.0), rng.randint(-14, 23))
+        for delta in (-3e-8, 3e-8, rng.uniform(-3e-8, 3e-8)):
+            got = recip_emulated(d, delta)
+            with mp.workdps(40):
+                exact = 1 / mp.mpf(d)
+                err = float(abs(mp.mpf(got) - exact) / mp.mpf(math.ulp(float(exact))))
+            worst = max(worst, err)
+    assert worst <= 1.0, worst
