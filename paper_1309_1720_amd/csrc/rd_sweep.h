@@ -93,6 +93,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 // Waves per workgroup of the sweep kernels (consecutive bands of a strip).
 constexpr int kSweepWaves = 4;
 
+// The boundary rule inside a sweep: read from the constants at run time, or
+// compiled in (no-flux, periodic).  Compiled in, its tests fold and the
+// steady iterations lose their wrap logic and the scalar registers it holds
+// (FK 1024^2 23.8 -> 22.7 us); the Bueno-Orovio step measured slower that way
+// (148 -> 156-163 us) and reads it at run time.
+enum { kBoundaryRuntime = 0, kBoundaryNoFlux = 1, kBoundaryPeriodic = 2 };
+
 // Kernel variants of the fused step (identical results): one wave carrying
 // every stage (rd_sweep.h) or one wave per stage (rd_pipe.h).
 enum StepVariant { kVariantSweep = 0, kVariantPipe = 1 };
@@ -118,10 +125,14 @@ template <int MODEL, int NS, int MODE> struct SweepPrefetch {
 // FR: ramp-up iterations with compile-time stage activity (below); off where
 // the larger code would not stay in the instruction cache.
 template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1, int GATE = 0, int HK = kHkAny,
-          bool FR = true>
+          bool FR = true, int PB = kBoundaryRuntime>
 __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double* const* out,
                                                 double* const (*ys)[kMaxFields], const KConst& c,
                                                 int wid) {
+  // PB: the boundary rule read from c, or fixed at compile time (its tests
+  // then fold); row indices wrap (periodic) or clamp (no-flux)
+  const bool PER = PB == kBoundaryRuntime ? c.periodic != 0 : PB == kBoundaryPeriodic;
+  auto row_index = [&](int y) { return PER ? wrap_index(y, c.ny) : min(max(y, 0), c.ny - 1); };
   static_assert(K == 1 || MODE == kModeStep, "several steps per launch advance the state only");
   static_assert(GATE == 0 || (NS == 1 && K == 1), "gate schemes have one stage");
   constexpr bool TAN = MODE == kModeTangent;
@@ -141,16 +152,16 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   const int sx = wid / c.nby;  // bands of one strip are consecutive
   const int by = wid % c.nby;
   const int gx = sx * TX - KS + lane;
-  const int cx = grid_index(gx, c.nx, c);
+  const int cx = PER ? wrap_index(gx, c.nx) : min(max(gx, 0), c.nx - 1);
   const bool out_col = lane >= KS && lane < KS + TX && gx < c.nx;
   const Column col = make_column(gx, c, STENCIL == RD_LAP9_ANISO);
 
   const int yA = by * c.ty;
   const int yB = min(yA + c.ty, c.ny);
   // periodic grids run the ramps through the wrapped rows
-  const int r_first = c.periodic ? yA - KS : max(yA - KS, 0);
+  const int r_first = PER ? yA - KS : max(yA - KS, 0);
   const int r_last = yB - 1 + KS;
-  const int load_end = c.periodic ? yB + KS : min(yB + KS, c.ny);
+  const int load_end = PER ? yB + KS : min(yB + KS, c.ny);
   const size_t nx = (size_t)c.nx;
 
   // Per step copy k: register rings indexed by rows relative to its input row
@@ -192,7 +203,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   double pre[PF][NF];
 #pragma unroll
   for (int p = 0; p < PF; ++p) {
-    const int row = grid_index(min(r_first + p, load_end - 1), c.ny, c);
+    const int row = row_index(min(r_first + p, load_end - 1));
 #pragma unroll
     for (int f = 0; f < NF; ++f) pre[p][f] = 0.0;
     if (row >= 0) {
@@ -254,7 +265,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
 #pragma unroll
           for (int f = 0; f < NF; ++f) pre[p][f] = pre[p + 1][f];
       }
-      const size_t o = (size_t)grid_index(min(r + PF, load_end - 1), c.ny, c) * nx + cx;
+      const size_t o = (size_t)row_index(min(r + PF, load_end - 1)) * nx + cx;
 #pragma unroll
       for (int f = 0; f < NF; ++f) pre[SLOT < 0 ? PF - 1 : q][f] = in[f][o];
     }
@@ -277,8 +288,8 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         if (UP) {
           if (PHASE - 1 < 2 * (k * NS + s)) continue;  // folded
         } else if (!STEADY) {
-          const int lo = c.periodic ? yA - (K - k) * NS + s : max(yA - (K - k) * NS + s, 0);
-          const int hi = c.periodic ? yB + (K - k) * NS - s : min(yB + (K - k) * NS - s, c.ny);
+          const int lo = PER ? yA - (K - k) * NS + s : max(yA - (K - k) * NS + s, 0);
+          const int hi = PER ? yB + (K - k) * NS - s : min(yB + (K - k) * NS - s, c.ny);
           if (rho < lo || rho >= hi) continue;  // wave-uniform
         }
 
@@ -305,8 +316,8 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
         if (!FIXED) {
 #pragma unroll
           for (int d = 0; d < ND; ++d) {
-            if (!c.periodic && rho == 0) up[d] = y[comp(d)];
-            if (!c.periodic && rho == c.ny - 1) dn[d] = y[comp(d)];
+            if (!PER && rho == 0) up[d] = y[comp(d)];
+            if (!PER && rho == c.ny - 1) dn[d] = y[comp(d)];
           }
         }
 
@@ -390,7 +401,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   // (one iteration later with the carried face fluxes: every stage must have
   // run on the row above its first steady row)
   constexpr int CL = CARRY ? 1 : 0;
-  const int ss_lo = min(c.periodic ? yA + KS + CL : max(yA + KS + CL, KS + 1), r_last + 1);
+  const int ss_lo = min(PER ? yA + KS + CL : max(yA + KS + CL, KS + 1), r_last + 1);
   const int ss_hi = max(load_end, ss_lo);
   const int ss_end = ss_lo + (ss_hi - ss_lo) / PF * PF;
   using Gen = std::integral_constant<int, 0>;
@@ -411,7 +422,7 @@ __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double*
   // Fixed ramp-up: rows r_first = yA - KS .. ss_lo - 1 lie at least one row
   // inside both y-edges (stage rows yA - KS + s .. yA + KS + CL - 2), and
   // every stage row is before its range end.
-  if (!c.periodic && yA >= KS && yA + 2 * KS + 1 < c.ny) {
+  if (!PER && yA >= KS && yA + 2 * KS + 1 < c.ny) {
     static_for<2 * KS + CL>([&](auto i) {
       constexpr int I = decltype(i)::value;
       iter(r_first + I, std::false_type{}, Shift{}, std::integral_constant<int, 1 + I>{});
@@ -439,10 +450,18 @@ __device__ __forceinline__ void sweep_wave(const double* const* in, double* cons
                                            double* const (*ys)[kMaxFields], const KConst& c,
                                            int wid) {
   const int x0 = (wid / c.nby) * (kWave - 2 * K * NS) - K * NS;
-  if (strip_touches_edge(x0, c))
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR>(in, out, ys, c, wid);
-  else
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK, FR>(in, out, ys, c, wid);
+  if constexpr (MODEL == RD_MODEL_BOCF) {
+    if (strip_touches_edge(x0, c))
+      sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR>(in, out, ys, c, wid);
+    else
+      sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK, FR>(in, out, ys, c, wid);
+  } else if (c.periodic) {
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR, kBoundaryPeriodic>(in, out, ys, c, wid);
+  } else if (strip_touches_edge(x0, c)) {
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR, kBoundaryNoFlux>(in, out, ys, c, wid);
+  } else {
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK, FR, kBoundaryNoFlux>(in, out, ys, c, wid);
+  }
 }
 
 template <int MODEL, int STENCIL, int NS, int MODE, int K, int GATE, int HK>
