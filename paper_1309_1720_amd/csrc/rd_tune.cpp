@@ -148,8 +148,10 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
   if (cands.empty()) cands.push_back(fallback);
 
   // Two passes over the candidates, keeping each one's faster pass: the
-  // first pass also brings the clocks up, which would otherwise favour the
-  // candidates timed last.
+  // first pass (three launches each) also brings the clocks up, which would
+  // otherwise favour the candidates timed last; the second repeats each
+  // candidate for about 0.3 ms (3 to 50 launches), so that short launches
+  // are not ranked by timer noise.
   hipEvent_t e0 = nullptr, e1 = nullptr;
   Plan best = fallback;
   bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
@@ -157,7 +159,8 @@ Plan tuned_plan(int kind, int model, int stencil, int scheme, int nx, int ny, in
   std::vector<float> per_step(cands.size(), 1e30f);
   for (int pass = 0; pass < 2; ++pass)
     for (size_t i = 0; ok && i < cands.size(); ++i) {
-      const int reps = 3;
+      const float launch_ms = per_step[i] * (float)cands[i].k;
+      const int reps = pass == 0 ? 3 : std::max(3, std::min(50, (int)(0.3f / std::max(launch_ms, 1e-3f)) + 1));
       ok = hipEventRecord(e0, s) == hipSuccess;
       for (int r = 0; ok && r < reps; ++r) ok = trial(cands[i]) == hipSuccess;
       ok = ok && hipEventRecord(e1, s) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
