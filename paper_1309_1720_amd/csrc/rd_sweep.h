@@ -455,8 +455,8 @@ __device__ __forceinline__ void sweep_wave(const double* const* in, double* cons
       sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR>(in, out, ys, c, wid);
     else
       sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK, FR>(in, out, ys, c, wid);
-  } else if (c.periodic) {
-    sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR, kBoundaryPeriodic>(in, out, ys, c, wid);
+  } else if (c.periodic) {  // no x-edge either: every strip wraps
+    sweep_wave_impl<MODEL, STENCIL, NS, MODE, false, K, GATE, HK, FR, kBoundaryPeriodic>(in, out, ys, c, wid);
   } else if (strip_touches_edge(x0, c)) {
     sweep_wave_impl<MODEL, STENCIL, NS, MODE, true, K, GATE, HK, FR, kBoundaryNoFlux>(in, out, ys, c, wid);
   } else {
