@@ -525,7 +525,8 @@ def other_workloads(rd, torch, dev, only=None, steps: int = 200):
         out["barkley_1024_rk4_adjoint_4000"] = {
             "forward_seconds": sec_fwd, "vjp_seconds": sec_vjp, "vjp_over_forward": sec_vjp / sec_fwd,
             "forward_rate": cells * w["nsteps"] / sec_fwd, "forward_steps_per_launch": rd.get_steps_per_launch(p),
-            "forward_hbm_frac": 32 * cells * w["nsteps"] / sec_fwd / HBM_PEAK}
+            "forward_hbm_frac": 32 * cells * w["nsteps"] / sec_fwd / HBM_PEAK,
+            "forward_tile_rows": rd.get_tile_rows(p, "step"), "adjoint_tile_rows": rd.get_tile_rows(p, "vjp")}
     return out
 
 

@@ -325,7 +325,8 @@ int rd_get_steps_per_launch(const rd_problem* p, int32_t* steps);
 
 /* Band height the library uses for `op` (RD_OP_STEP, RD_OP_JVP, RD_OP_VJP) on
  * problem `p`: the override, else the autotuner's cached choice, else its
- * heuristic starting value. */
+ * heuristic starting value.  For RD_OP_VJP, the band height of the reverse
+ * step's adjoint kernel (the fused one where rd_vjp runs it). */
 int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows);
 
 /* Enables (non-zero, the default) or disables the band-height autotuner.

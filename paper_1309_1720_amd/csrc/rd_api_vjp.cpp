@@ -36,7 +36,7 @@ static hipError_t launch_adjoint_fused_kernel(int model, int stencil, int scheme
 
 // Whether rd_vjp's reverse step recomputes the stage inputs in the adjoint
 // kernel (rd_adjoint_fused.h) for this problem.
-static bool fused_adjoint(const rd_problem* p) {
+bool fused_adjoint(const rd_problem* p) {
   return g_fused_adjoint.load() && n_fields(p->model) <= 2 && p->bc == RD_BC_NOFLUX && !is_3d(p->stencil) &&
          (p->scheme == RD_SCHEME_HEUN || p->scheme == RD_SCHEME_RK4);
 }

@@ -68,5 +68,8 @@ size_t workspace_vjp_3d(const rd_problem* p);
 int vjp_3d(const rd_problem* p, const KConst& c, const double* checkpoints, double* const* cot, char* ws,
            hipStream_t s);
 int workspace_vjp(const rd_problem* p, size_t* out);
+// Whether rd_vjp runs the fused reverse step (stage inputs recomputed in the
+// adjoint kernel, halo 2 NS - 2 rows and columns) for this problem.
+bool fused_adjoint(const rd_problem* p);
 
 }  // namespace rd

@@ -270,6 +270,10 @@ int rd_get_tile_rows(const rd_problem* p, int32_t op, int32_t* rows) {
     default: return rd::fail(RD_EINVAL, "rd_get_tile_rows: op %d has no single-grid band height", op);
   }
   const int ns = rd::n_stages(p->scheme);
+  if (op == RD_OP_VJP && rd::fused_adjoint(p)) {  // the fused reverse step's own band height
+    *rows = rd::current_rows(rd::kTuneAdjointFused, p->model, p->stencil, p->scheme, p->nx, p->ny, 2 * ns - 2);
+    return RD_OK;
+  }
   *rows = op == RD_OP_VJP ? rd::current_rows(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns)
                           : rd::current_plan(kind, p->model, p->stencil, p->scheme, p->nx, p->ny, ns, true,
                                              op == RD_OP_STEP ? rd::max_steps_per_launch(p->model, ns) : 1).ty;
