@@ -85,8 +85,9 @@ void batch_sweep_kernel(BatchArgs a) {
     out[f] = a.parity ? I.a[f] : I.b[f];
   }
   double* const no_stages[3][kMaxFields] = {};
-  // The tangent step's compile-time ramps (a third more code) measured slower
-  // here: the instances' waves run different parts of the kernel at once.
+  // The tangent step keeps the former loop structure: with the compile-time
+  // ramps and the two-row steady unroll (a third more code) it measured 8-12%
+  // slower here, although the single-grid tangent step gains from them.
   sweep_wave<MODEL, STENCIL, NS, MODE, 1, GATE, HK, MODE != kModeTangent>(in, out, no_stages, c, wid - I.wave_begin);
 }
 

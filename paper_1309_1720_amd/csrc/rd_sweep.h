@@ -122,8 +122,9 @@ template <int MODEL, int NS, int MODE> struct SweepPrefetch {
 // of z_{n+k} (the row copy k - 1 finished in the same iteration; copy 0 the
 // row just loaded) and runs its stage s on row r - k NS - s, so the launch
 // needs KS = K NS halo columns and ramp rows.
-// FR: ramp-up iterations with compile-time stage activity (below); off where
-// the larger code would not stay in the instruction cache.
+// FR: ramp-up iterations with compile-time stage activity (below), and the
+// steady run unrolled by at least two rows; off, the former loop structure
+// (kept where it measured faster: the batched tangent step).
 template <int MODEL, int STENCIL, int NS, int MODE, bool EDGE, int K = 1, int GATE = 0, int HK = kHkAny,
           bool FR = true, int PB = kBoundaryRuntime>
 __device__ __forceinline__ void sweep_wave_impl(const double* const* in, double* const* out,
