@@ -349,20 +349,28 @@ def _calibration(out: str):
     return CALIB_BYTES / 1024 / f_c, CALIB_BYTES / 1024 / w_c
 
 
-def _kernel_table(out: str, kinds, cal_dir: str, title: str, cmd):
+def _kernel_table(out: str, kinds, cal_dir: str, title: str, cmd, cells: int = 0):
     """Per-kernel timing (median dispatch) and counter traffic against the
     algorithmic bytes each launch must move.  kinds: (name prefix, role,
-    algorithmic bytes per launch)."""
+    algorithmic bytes per launch).  With OUT/sq (a run counting SQ_WAVES and
+    SQ_INSTS_VALU) and the cells one launch updates, also the VALU
+    lane-instructions per cell and launch and the share of the VALU issue
+    capacity at the median dispatch."""
     fs, wsc = _calibration(cal_dir)
     fetch = _counters(os.path.join(out, "fetch"))
     write = _counters(os.path.join(out, "write"))
+    sq = _counters(os.path.join(out, "sq")) if cells and os.path.isdir(os.path.join(out, "sq")) else None
     stats = _rows(os.path.join(out, "stats"), "*kernel_stats.csv")
-    lines = [f"# {title}", "", "Commands (each a run of its own):", "",
-             "    " + cmd("--kernel-trace --stats"), "    " + cmd("--pmc FETCH_SIZE"), "    " + cmd("--pmc WRITE_SIZE"),
+    head = "| kernel | role | calls | median us | algorithmic MB | algorithmic GB/s | of 8 TB/s | HBM MB | HBM / algorithmic |"
+    rule = "|---|---|---|---|---|---|---|---|---|"
+    cmds = ["    " + cmd("--kernel-trace --stats"), "    " + cmd("--pmc FETCH_SIZE"), "    " + cmd("--pmc WRITE_SIZE")]
+    if sq is not None:
+        head += " VALU lane-instr per cell | VALU issue |"
+        rule += "---|---|"
+        cmds.append("    " + cmd("--pmc SQ_WAVES SQ_INSTS_VALU"))
+    lines = [f"# {title}", "", "Commands (each a run of its own):", "", *cmds,
              "", f"HBM bytes: FETCH_SIZE x {fs:.3f} + WRITE_SIZE x {wsc:.3f} per dispatch (the factors a plain copy of "
-             "2^26 doubles reads in the headline's counter runs).", "",
-             "| kernel | role | calls | median us | algorithmic MB | algorithmic GB/s | of 8 TB/s | HBM MB | HBM / algorithmic |",
-             "|---|---|---|---|---|---|---|---|---|"]
+             "2^26 doubles reads in the headline's counter runs).", "", head, rule]
     med = {}
     for needle, role, alg in kinds:
         row = [r for r in stats if r["Name"].startswith("void " + needle)]
@@ -373,8 +381,12 @@ def _kernel_table(out: str, kinds, cal_dir: str, title: str, cmd):
         med[needle] = m
         f_k, w_k = _pick(fetch, needle, "FETCH_SIZE"), _pick(write, needle, "WRITE_SIZE")
         hbm = (f_k * fs + w_k * wsc) * 1024
-        lines.append(f"| `{needle}` | {role} | {row[0]['Calls']} | {m:.2f} | {alg / 1e6:.1f} | {alg / m / 1e3:.0f} | "
-                     f"{alg / m / 1e3 / 8000 * 100:.0f}% | {hbm / 1e6:.1f} | {hbm / alg:.2f} |")
+        line = (f"| `{needle}` | {role} | {row[0]['Calls']} | {m:.2f} | {alg / 1e6:.1f} | {alg / m / 1e3:.0f} | "
+                f"{alg / m / 1e3 / 8000 * 100:.0f}% | {hbm / 1e6:.1f} | {hbm / alg:.2f} |")
+        if sq is not None:
+            lanes = _pick(sq, needle, "SQ_INSTS_VALU") * 64
+            line += f" {lanes / cells:.0f} | {lanes / (m * 1e-6) / bench.VALU_LANE_ISSUE_PEAK * 100:.0f}% |"
+        lines.append(line)
     return med, lines
 
 
@@ -396,7 +408,7 @@ def main_ensemble(out: str, cal_dir: str) -> None:
     med, lines = _kernel_table(out, [(fwd, "one RK4 step of all 64 members", 48 * cells),
                                      (tan, "one RK4 step of all members and their tangents", 96 * cells)],
                                cal_dir, "Batched ensemble, 64 Fenton-Karma members (9-point, RK4, FP64) — one launch "
-                               "per step", cmd)
+                               "per step", cmd, cells)
     lines += ["", f"{cells} cells per launch (16 each of 256^2, 384^2, 512^2, 768^2).  Algorithmic bytes: the state "
                   "(48 B per cell) or the state and tangent (96 B) read and written once.  The tangent step costs "
                   f"{med[tan] / med[fwd]:.2f}x the forward step."]
@@ -428,7 +440,7 @@ def main_adjoint(out: str, cal_dir: str) -> None:
         kinds += [(stg, "stage inputs Y2..Y4 of one step (reads z, writes three states)", 8 * field),
                   (adj, "one reverse step (reads z, Y2..Y4, lambda; writes lambda)", 12 * field)]
     med, lines = _kernel_table(out, kinds, cal_dir, "Adjoint workload, Barkley 1024x1024 (5-point, RK4, FP64) — "
-                               "forward and reverse kernels", cmd)
+                               "forward and reverse kernels", cmd, cells)
     fwd_step = med[fwd2] / 2 if fwd2 in med else med[rec1]
     if fused in med:
         rev = med[fused] + med[rec1]
