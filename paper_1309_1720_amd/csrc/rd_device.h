@@ -412,8 +412,18 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     T h_vm;
     hk_pair<HK>(u - m.th_vm, c, h_vm, t.v_inf);  // v_inf = H(th_v^- - u)
     t.h_o = hk<HK>(u - m.th_o, c);
-    t.r_vm = recip(mad(h_vm, m.dtau_vm, T(m.tau_v1m)));                 // tau_v1^- + H (tau_v2^- - tau_v1^-)
-    t.r_wm = logistic_blend_recip(mad(u, m.lg_wm_a, m.lg_wm_b), m.tau_w1m, m.tau_w2m);
+    // 1/tau_v^- and 1/tau_w^- (tau_w^- = (E tau_w1^- + tau_w2^-) / (1 + E), the
+    // logistic blend) from one reciprocal of the product of the two
+    // denominators; each product holds at most one exponential (capped), so it
+    // stays finite.  One FP64 reciprocal costs about as much as four FMAs.
+    {
+      const T E_wm = exp_capped(mad(u, m.lg_wm_a, m.lg_wm_b));
+      const T d_wm = mad(E_wm, m.tau_w1m, T(m.tau_w2m));
+      const T t_vm = mad(h_vm, m.dtau_vm, T(m.tau_v1m));
+      const T R = recip(t_vm * d_wm);
+      t.r_vm = R * d_wm;
+      t.r_wm = (1.0 + E_wm) * (t_vm * R);
+    }
     t.r_s = recip(mad(t.h_w, m.dtau_s, T(m.tau_s1)));                  // tau_s1 + H (tau_s2 - tau_s1)
     // w_inf = (1 - H_o)(1 - u / tau_winf) + H_o w_inf*
     const T a = mad(-u, m.inv_tau_winf, 1.0);
@@ -441,8 +451,13 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     const BocfC& m = c.m.bo;
     const T u = y[0], v = y[1], w = y[2], s = y[3];
     const BocfTerms<T> t = terms<T, HK>(c, u);
-    const T r_so = logistic_blend_recip(mad(u, m.lg_so_a, m.lg_so_b), m.tau_so1, m.tau_so2);  // 1/tau_so
-    const T r_o = recip(mad(t.h_o, m.dtau_o, T(m.tau_o1)));                                   // 1/tau_o
+    // 1/tau_so (logistic blend) and 1/tau_o from one reciprocal, as above.
+    const T E_so = exp_capped(mad(u, m.lg_so_a, m.lg_so_b));
+    const T d_so = mad(E_so, m.tau_so1, T(m.tau_so2));
+    const T t_o = mad(t.h_o, m.dtau_o, T(m.tau_o1));
+    const T R = recip(t_o * d_so);
+    const T r_so = (1.0 + E_so) * (t_o * R);
+    const T r_o = R * d_so;
     const T j_fi = -(((v * t.h_v) * (u - m.th_v)) * (m.u_u - u)) * m.inv_tau_fi;
     const T j_so = mad((u - m.u_o) * t.h_w_neg, r_o, t.h_w * r_so);
     const T j_si = -((t.h_w * w) * s) * m.inv_tau_si;
@@ -453,7 +468,10 @@ template <> struct Reaction<RD_MODEL_BOCF> {
     const T alpha_w = mad(-t.h_w, m.inv_tau_wp, -(t.h_w_neg * t.r_wm));
     const T beta_w = (t.h_w_neg * t.w_inf) * t.r_wm;
     f[2] = mad(alpha_w, w, beta_w);
-    f[3] = (t.s_inf - s) * t.r_s;
+    // (s_inf - s) / tau_s with s_inf = 1 / (1 + E) written as
+    // (1 - s (1 + E)) / ((1 + E) tau_s): one reciprocal instead of two.
+    const T one_e = 1.0 + exp_capped(mad(u, m.lg_s_a, m.lg_s_b));
+    f[3] = mad(-s, one_e, T(1.0)) * recip(one_e * mad(t.h_w, m.dtau_s, T(m.tau_s1)));
   }
 };
 
